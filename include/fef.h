@@ -1,0 +1,177 @@
+/*
+ * fef.h - C ABI of the MI355X (gfx950) FEF pair-energy / effective-field
+ * library.
+ *
+ * Method: fragment-effective-field coupled-cluster perturbation theory
+ * (FEF-CCPT), arXiv:1708.03377.  The library computes, for a system of
+ * molecular fragments in the product (A ~ 1) ansatz:
+ *
+ *   - the half-transformed factored inter-fragment integrals
+ *       B^x_ov[P][ia] = sum_{mu nu} C^x_{mu i} B^x[P][mu][nu] C^x_{nu a}
+ *     and W^x = G_{c(x),0}^T B^x_ov  (fef_half_transform);
+ *   - the dimer second-order pair energies of Eq. ED2 with the first-order
+ *     dimer doubles of Eq. dimDoubles (diagonal canonical F^[0]):
+ *       E2_xy = 4 sum_{ia,jb} (ia|jb)^2 / (eps_i + eps_j - eps_a - eps_b),
+ *       (ia|jb) = s_xy sum_Q W^x[Q][ia] B^y_ov[Q][jb]      (fef_pair_energies);
+ *   - the effective Coulomb field 2 v^{mu j}_{nu j} of Eqs. wc and dp2e
+ *     (fef_coulomb_field);
+ *   - one polarisation-screened SCF update of every fragment
+ *     F~ = F0 + h~ + J, (eps, C) = eigh(F~), Aufbau occupation
+ *     (fef_scf_step; Sec. II.A, "Fragment Mean Field").
+ *
+ * Integral model: (mu nu|lambda sigma)^{xy} = sum_PQ B^x_{P mu nu} T^{xy}_{PQ}
+ * B^y_{Q lambda sigma} with T^{xy} = s_xy G_{c(x),c(y)}, s_xy = 1/R_xy
+ * (bohr^-1) and G_{0,c} = G_{c,0}^T.  Class 0 is the solvent class; every
+ * pair must contain at least one class-0 fragment.
+ *
+ * Conventions
+ *   Units: Hartree and bohr.  Row-major throughout.  MO order within a
+ *   fragment: occupied first.  ia index = i * nvir + a (i-major).
+ *   Pools: per-fragment arrays are densely concatenated in fragment order:
+ *     B   [P_c][nbf][nbf]  symmetric in (mu, nu)
+ *     C   [nbf][nbf]       column p = MO p
+ *     F0, htilde, D, J     [nbf][nbf]
+ *     eps [nbf]
+ *     Bov [P_c][nocc*nvir],  W [P_0][nocc*nvir]
+ *     G   concatenation over classes c of G_{c,0}, [P_c][P_0]; G_{0,0}
+ *         must be symmetric.
+ *   Pointers passed to compute calls are DEVICE pointers owned by the
+ *   caller; the compute calls never allocate or free, run asynchronously on
+ *   `stream` (a hipStream_t, NULL = default stream) and return after
+ *   enqueueing.  Sizes of the opaque operand pool and of every workspace come
+ *   from fef_plan_query.
+ *   Errors: argument problems detectable on the host return a negative
+ *   status synchronously and enqueue nothing; a failed launch returns
+ *   FEF_E_HIP.  Data-dependent conditions are reported in the device word
+ *   `flags` (read it after synchronising): bit 0 = some fragment has a
+ *   non-positive HOMO-LUMO gap, bit 1 = a non-finite pair energy.  The
+ *   library never clears `flags`; the caller zeroes it.
+ *   No C++ exception crosses this interface.
+ */
+#ifndef FEF_H
+#define FEF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fef_status;
+#define FEF_OK 0
+#define FEF_E_ARG -1          /* null pointer or invalid argument      */
+#define FEF_E_SHAPE -2        /* inconsistent sizes / unsupported pair */
+#define FEF_E_PREC -3         /* unknown precision mode                */
+#define FEF_E_WORKSPACE -4    /* workspace too small                   */
+#define FEF_E_HIP -5          /* HIP runtime error                     */
+#define FEF_E_UNSUPPORTED -6  /* valid request the library cannot do   */
+
+#define FEF_FLAG_GAP 1
+#define FEF_FLAG_NONFINITE 2
+
+/* Arithmetic of the pair contraction (a reduced-precision mode rounds the
+ * half-transformed operands; every other step stays FP64). */
+typedef enum {
+  FEF_F64 = 0,     /* FP64 operands, FP64 MFMA                              */
+  FEF_F32 = 1,     /* FP32 operands, FP32 MFMA                              */
+  FEF_BF16X2 = 2,  /* x = hi + lo in BF16; hi*hi' + hi*lo' + lo*hi', FP32 acc */
+  FEF_FP16X2 = 3,  /* same with FP16 and a per-fragment power-of-two scale  */
+  FEF_NPREC = 4
+} fef_prec;
+
+/* Fragment system, HOST memory, read once by fef_plan_create. */
+typedef struct {
+  int32_t nfrag;
+  int32_t nclass;
+  const int32_t* nbf;     /* [nfrag] basis functions per fragment          */
+  const int32_t* nocc;    /* [nfrag] doubly occupied orbitals, 0..nbf      */
+  const int32_t* cls;     /* [nfrag] class id in [0, nclass)               */
+  const int32_t* naux;    /* [nclass] factor rank P_c                      */
+  int64_t npair;
+  const int32_t* pair_x;  /* [npair] fragment ids, x != y; every pair once */
+  const int32_t* pair_y;
+  const double* pair_s;   /* [npair] s_xy = 1/R_xy in bohr^-1              */
+} fef_system_desc;
+
+typedef struct fef_plan_s* fef_plan;
+
+/* Builds the device tables (fragment offsets, oriented pairs, work items,
+ * neighbour lists) on the current HIP device.  Allocates device memory; call
+ * outside graph capture.  The neighbour set of the field is the pair list
+ * itself (both orientations). */
+fef_status fef_plan_create(const fef_system_desc* desc, fef_plan* out);
+fef_status fef_plan_destroy(fef_plan plan);
+
+typedef enum {
+  FEF_Q_OPS_BYTES = 0,      /* operand pool written by fef_half_transform */
+  FEF_Q_HALF_WS_BYTES = 1,  /* workspace of fef_half_transform           */
+  FEF_Q_PAIR_WS_BYTES = 2,  /* workspace of fef_pair_energies            */
+  FEF_Q_FIELD_WS_BYTES = 3, /* workspace of fef_coulomb_field            */
+  FEF_Q_SCF_WS_BYTES = 4,   /* workspace of fef_scf_step                 */
+  FEF_Q_BOV_ELEMS = 5,      /* doubles in the dense Bov pool             */
+  FEF_Q_W_ELEMS = 6,        /* doubles in the dense W pool               */
+  FEF_Q_NITEMS = 7,         /* pair-kernel work items                    */
+  FEF_Q_B_ELEMS = 8,        /* doubles in the B pool                     */
+  FEF_Q_C_ELEMS = 9,        /* doubles in a C / D / F0 / J pool          */
+  FEF_Q_EPS_ELEMS = 10,     /* doubles in the eps pool                   */
+  FEF_Q_G_ELEMS = 11,       /* doubles in the G pool                     */
+  FEF_Q_NPAIR = 12
+} fef_query;
+
+/* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES and
+ * FEF_Q_PAIR_WS_BYTES; it is ignored otherwise. */
+fef_status fef_plan_query(fef_plan plan, fef_query what, fef_prec prec,
+                          int64_t* out);
+
+/* Half transform (the x-side half of the four-index AO->MO transform).
+ *   B, C, G : input pools (device).
+ *   Bov, W  : optional dense FP64 outputs (device, may be NULL).
+ *   ops     : opaque operand pool for fef_pair_energies in mode `prec`,
+ *             FEF_Q_OPS_BYTES bytes (device, required).
+ *   ws      : workspace of FEF_Q_HALF_WS_BYTES bytes. */
+fef_status fef_half_transform(fef_plan plan, const double* B, const double* C,
+                              const double* G, double* Bov, double* W,
+                              void* ops, fef_prec prec, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Pair energies (Eq. ED2 with the amplitudes of Eq. dimDoubles).
+ *   ops      : operand pool written by fef_half_transform in the same mode.
+ *   eps      : orbital-energy pool (canonical, ascending within occ / vir).
+ *   E2_pair  : [npair] out, in the caller's pair order (device).
+ *   E2_total : [1] out, FP64 sum over pairs in a fixed order (device).
+ *   flags    : [1] device word, bits are OR-ed in.
+ * The result is bitwise reproducible for a given plan and mode. */
+fef_status fef_pair_energies(fef_plan plan, const void* ops, const double* eps,
+                             fef_prec prec, double* E2_pair, double* E2_total,
+                             int32_t* flags, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* Effective Coulomb field (Eqs. wc, dp2e):
+ *   J^x_{mu nu} = 2 sum_{y in nbr(x)} sum_{lambda sigma}
+ *                 (mu nu|lambda sigma)^{xy} D^y_{lambda sigma}
+ * evaluated as 2 sum_P B^x_{P mu nu} (sum_y T^{xy} d^y)_P, d^y = B^y : D^y.
+ *   D : density pool (D = C_occ C_occ^T, no factor 2), J : output pool. */
+fef_status fef_coulomb_field(fef_plan plan, const double* B, const double* G,
+                             const double* D, double* J, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* One simultaneous SCF update of every fragment:
+ *   D_in = C_occ C_occ^T from the input C; F~ = F0 + h~ + J[D_in];
+ *   (eps, C) = eigh(F~) ascending (ties by index), lowest nocc occupied;
+ *   D = C_occ C_occ^T of the new C.
+ *   C      : in/out pool; eps : out pool; D : optional out pool (NULL ok).
+ *   htilde : optional additive one-electron field pool (NULL = zero).
+ *   dD_max : [1] device out, max |D - D_in| over all fragments.
+ *   flags  : bit 0 set when a fragment's new HOMO-LUMO gap is <= 0. */
+fef_status fef_scf_step(fef_plan plan, const double* B, const double* G,
+                        const double* F0, const double* htilde, double* C,
+                        double* eps, double* D, double* dD_max, int32_t* flags,
+                        void* ws, size_t ws_bytes, void* stream);
+
+const char* fef_status_string(fef_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEF_H */

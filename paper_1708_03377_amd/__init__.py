@@ -1,0 +1,15 @@
+"""MI355X (gfx950) FEF pair energies and effective-field SCF.
+
+The computation lives in the HIP library ``libfef.so`` behind the C ABI of
+include/fef.h; ``_fef`` binds it with ctypes and ``runtime.Context`` holds the
+device buffers of one fragment system.
+"""
+from . import _fef  # noqa: F401
+from ._fef import (PREC, FefError, fef_coulomb_field, fef_half_transform,  # noqa: F401
+                   fef_pair_energies, fef_plan_create, fef_plan_query, fef_scf_step,
+                   fef_status_string, load_library)
+
+
+def Context(*args, **kwargs):
+    from .runtime import Context as _C
+    return _C(*args, **kwargs)

@@ -1,0 +1,177 @@
+"""ctypes binding of ``libfef.so`` (C ABI in include/fef.h).
+
+Argument marshalling only: every function here has the C entry point's name,
+turns tensors into device pointers and checks the returned status.  No
+arithmetic of the method happens here.  A missing library is an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfef.so")
+
+FEF_OK = 0
+FEF_E_ARG = -1
+FEF_E_SHAPE = -2
+FEF_E_PREC = -3
+FEF_E_WORKSPACE = -4
+FEF_E_HIP = -5
+FEF_E_UNSUPPORTED = -6
+FEF_FLAG_GAP = 1
+FEF_FLAG_NONFINITE = 2
+
+PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
+
+Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
+Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
+
+# every entry point declared in include/fef.h
+ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
+                "fef_half_transform", "fef_pair_energies", "fef_coulomb_field",
+                "fef_scf_step", "fef_status_string")
+
+
+class FefError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} failed with status {status}: {msg}")
+        self.status = status
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("nfrag", ctypes.c_int32), ("nclass", ctypes.c_int32),
+                ("nbf", ctypes.c_void_p), ("nocc", ctypes.c_void_p),
+                ("cls", ctypes.c_void_p), ("naux", ctypes.c_void_p),
+                ("npair", ctypes.c_int64),
+                ("pair_x", ctypes.c_void_p), ("pair_y", ctypes.c_void_p),
+                ("pair_s", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None) -> ctypes.CDLL:
+    """Loads libfef.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with "
+                           "`python -m paper_1708_03377_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(p)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.fef_plan_create.argtypes = [ctypes.POINTER(SystemDesc), ctypes.POINTER(vp)]
+    lib.fef_plan_destroy.argtypes = [vp]
+    lib.fef_plan_query.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    lib.fef_half_transform.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.fef_pair_energies.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
+    lib.fef_coulomb_field.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_scf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_status_string.argtypes = [i32]
+    lib.fef_status_string.restype = ctypes.c_char_p
+    for name in ENTRY_POINTS:
+        if name != "fef_status_string":
+            getattr(lib, name).restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def fef_status_string(status: int) -> str:
+    return load_library().fef_status_string(status).decode()
+
+
+def _check(fn: str, status: int):
+    if status != FEF_OK:
+        raise FefError(fn, status, fef_status_string(status))
+
+
+def _ptr(t) -> Optional[int]:
+    """Device (or host) address of a tensor / array, None for None."""
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _nbytes(t) -> int:
+    if t is None:
+        return 0
+    if isinstance(t, np.ndarray):
+        return t.nbytes
+    return t.numel() * t.element_size()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Plan:
+    """Owns a fef_plan handle and the host arrays it was created from."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load_library().fef_plan_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def fef_plan_create(nbf, nocc, cls, naux, pair_x, pair_y, pair_s) -> Plan:
+    lib = load_library()
+    arrs = [np.ascontiguousarray(nbf, dtype=np.int32),
+            np.ascontiguousarray(nocc, dtype=np.int32),
+            np.ascontiguousarray(cls, dtype=np.int32),
+            np.ascontiguousarray(naux, dtype=np.int32),
+            np.ascontiguousarray(pair_x, dtype=np.int32),
+            np.ascontiguousarray(pair_y, dtype=np.int32),
+            np.ascontiguousarray(pair_s, dtype=np.float64)]
+    d = SystemDesc(len(arrs[0]), len(arrs[3]), *(a.ctypes.data for a in arrs[:4]),
+                   len(arrs[4]), *(a.ctypes.data for a in arrs[4:]))
+    h = ctypes.c_void_p()
+    _check("fef_plan_create", lib.fef_plan_create(ctypes.byref(d), ctypes.byref(h)))
+    return Plan(h.value, arrs)
+
+
+def fef_plan_query(plan: Plan, what: int, prec: int = 0) -> int:
+    out = ctypes.c_int64()
+    _check("fef_plan_query", load_library().fef_plan_query(plan.handle, what, prec,
+                                                           ctypes.byref(out)))
+    return out.value
+
+
+def fef_half_transform(plan, B, C, G, Bov, W, ops, prec, ws, stream=None):
+    _check("fef_half_transform", load_library().fef_half_transform(
+        plan.handle, _ptr(B), _ptr(C), _ptr(G), _ptr(Bov), _ptr(W), _ptr(ops), prec,
+        _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_pair_energies(plan, ops, eps, prec, E2_pair, E2_total, flags, ws, stream=None):
+    _check("fef_pair_energies", load_library().fef_pair_energies(
+        plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(E2_pair), _ptr(E2_total), _ptr(flags),
+        _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_coulomb_field(plan, B, G, D, J, ws, stream=None):
+    _check("fef_coulomb_field", load_library().fef_coulomb_field(
+        plan.handle, _ptr(B), _ptr(G), _ptr(D), _ptr(J), _ptr(ws), _nbytes(ws),
+        _stream(stream)))
+
+
+def fef_scf_step(plan, B, G, F0, htilde, C, eps, D, dD_max, flags, ws, stream=None):
+    _check("fef_scf_step", load_library().fef_scf_step(
+        plan.handle, _ptr(B), _ptr(G), _ptr(F0), _ptr(htilde), _ptr(C), _ptr(eps), _ptr(D),
+        _ptr(dD_max), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))

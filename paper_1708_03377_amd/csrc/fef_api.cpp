@@ -1,0 +1,322 @@
+// Host side of the C ABI: argument checks, plan construction (fragment
+// offsets, oriented pairs, work items, neighbour lists) and dispatch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fef_internal.h"
+
+using namespace fef;
+
+namespace {
+
+template <class T>
+hipError_t upload(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_plan(fef_plan_s* p) {
+  if (!p) return;
+  void* ptrs[] = {p->d_frag, p->d_pair, p->d_item, p->d_ht, p->d_off_G, p->d_naux_cls_off,
+                  p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
+                  p->d_eig_mid, p->d_eig_large};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  delete p;
+}
+
+OpsGeom geom_of(int prec, int P0) {
+  switch (prec) {
+    case FEF_F64: return {8, (int)round_up(P0, 4)};
+    case FEF_F32: return {4, (int)round_up(P0, 4)};
+    default: return {2, (int)round_up(3 * (int64_t)P0, 32)};
+  }
+}
+
+bool valid_prec(int prec) { return prec >= 0 && prec < FEF_NPREC; }
+
+}  // namespace
+
+namespace fef {
+
+int64_t half_ws_bytes(const fef_plan_s& p, fef_prec) {
+  return (p.nBov + p.nW) * (int64_t)sizeof(double) + 256;
+}
+int64_t pair_ws_bytes(const fef_plan_s& p, fef_prec) {
+  return round_up(std::max<int64_t>(p.nitems, 1) * (int64_t)sizeof(double), 256);
+}
+static int64_t naux_total(const fef_plan_s& p) {
+  int64_t t = 0;
+  for (const auto& f : p.frag) t += f.naux;
+  return t;
+}
+int64_t field_ws_bytes(const fef_plan_s& p) {
+  return round_up(2 * std::max<int64_t>(naux_total(p), 1) * (int64_t)sizeof(double), 256);
+}
+int64_t scf_ws_bytes(const fef_plan_s& p) {
+  const int64_t large =
+      2 * (int64_t)p.eig_large.size() * p.eig_large_max_nbf * p.eig_large_max_nbf;
+  int64_t n = 3 * std::max<int64_t>(p.nC, 1) + large;
+  return field_ws_bytes(p) + round_up(n * (int64_t)sizeof(double), 256);
+}
+
+}  // namespace fef
+
+extern "C" {
+
+const char* fef_status_string(fef_status s) {
+  switch (s) {
+    case FEF_OK: return "ok";
+    case FEF_E_ARG: return "invalid argument";
+    case FEF_E_SHAPE: return "inconsistent sizes or unsupported pair";
+    case FEF_E_PREC: return "unknown precision mode";
+    case FEF_E_WORKSPACE: return "workspace too small";
+    case FEF_E_HIP: return "HIP runtime error";
+    case FEF_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
+  if (!d || !out) return FEF_E_ARG;
+  *out = nullptr;
+  if (d->nfrag < 0 || d->nclass < 1 || d->npair < 0) return FEF_E_ARG;
+  if (d->nfrag > 0 && (!d->nbf || !d->nocc || !d->cls)) return FEF_E_ARG;
+  if (!d->naux) return FEF_E_ARG;
+  if (d->npair > 0 && (!d->pair_x || !d->pair_y || !d->pair_s)) return FEF_E_ARG;
+  if (d->npair > (int64_t)INT32_MAX) return FEF_E_UNSUPPORTED;
+  for (int c = 0; c < d->nclass; ++c)
+    if (d->naux[c] < 1) return FEF_E_SHAPE;
+  for (int f = 0; f < d->nfrag; ++f) {
+    if (d->nbf[f] < 1 || d->nocc[f] < 0 || d->nocc[f] > d->nbf[f]) return FEF_E_SHAPE;
+    if (d->cls[f] < 0 || d->cls[f] >= d->nclass) return FEF_E_SHAPE;
+  }
+
+  fef_plan_s* p = new (std::nothrow) fef_plan_s();
+  if (!p) return FEF_E_UNSUPPORTED;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FEF_E_HIP; }
+  p->nfrag = d->nfrag;
+  p->nclass = d->nclass;
+  p->P0 = d->naux[0];
+  p->naux_cls.assign(d->naux, d->naux + d->nclass);
+  p->off_G.resize(d->nclass + 1);
+  p->off_G[0] = 0;
+  for (int c = 0; c < d->nclass; ++c)
+    p->off_G[c + 1] = p->off_G[c] + (int64_t)d->naux[c] * p->P0;
+  p->nG = p->off_G[d->nclass];
+  p->naux_cls_off.assign(d->nclass + 1, 0);
+  for (int c = 0; c < d->nclass; ++c) p->naux_cls_off[c + 1] = p->naux_cls_off[c] + d->naux[c];
+  for (int k = 0; k < FEF_NPREC; ++k) p->geom[k] = geom_of(k, p->P0);
+
+  // ---- fragment table -----------------------------------------------------
+  p->frag.resize(d->nfrag);
+  int64_t oB = 0, oC = 0, oE = 0, oBov = 0, oW = 0, oAux = 0;
+  int64_t oOps[FEF_NPREC];
+  // the operand pool starts with two scale factors per fragment (left, right)
+  p->ops_header = round_up(16 * (int64_t)std::max(d->nfrag, 1), 256);
+  for (int k = 0; k < FEF_NPREC; ++k) oOps[k] = p->ops_header;
+  for (int f = 0; f < d->nfrag; ++f) {
+    FragInfo& fi = p->frag[f];
+    std::memset(&fi, 0, sizeof(fi));
+    fi.nbf = d->nbf[f];
+    fi.nocc = d->nocc[f];
+    fi.nvir = fi.nbf - fi.nocc;
+    fi.ov = fi.nocc * fi.nvir;
+    fi.cls = d->cls[f];
+    fi.naux = d->naux[fi.cls];
+    fi.ntile = (int32_t)((fi.ov + kTile - 1) / kTile);
+    fi.ld = (int64_t)fi.ntile * kTile;
+    fi.off_B = oB;  oB += (int64_t)fi.naux * fi.nbf * fi.nbf;
+    fi.off_C = oC;  oC += (int64_t)fi.nbf * fi.nbf;
+    fi.off_eps = oE; oE += fi.nbf;
+    fi.off_bov = oBov; oBov += (int64_t)fi.naux * fi.ov;
+    fi.off_w = oW;  oW += (int64_t)p->P0 * fi.ov;
+    fi.off_aux = oAux; oAux += fi.naux;
+    for (int k = 0; k < FEF_NPREC; ++k) {
+      const int64_t blk = round_up((int64_t)p->geom[k].kpad * fi.ld * p->geom[k].elem_bytes, 256);
+      fi.off_L[k] = oOps[k];
+      oOps[k] += blk;
+      if (fi.cls == 0) { fi.off_R[k] = oOps[k]; oOps[k] += blk; }
+      else fi.off_R[k] = -1;
+    }
+    p->max_nbf = std::max(p->max_nbf, fi.nbf);
+    p->max_naux = std::max(p->max_naux, fi.naux);
+    p->max_ov = std::max(p->max_ov, fi.ov);
+    p->max_on = std::max<int64_t>(p->max_on, (int64_t)fi.nocc * fi.nbf);
+  }
+  p->nB = oB; p->nC = oC; p->nEps = oE; p->nBov = oBov; p->nW = oW;
+  for (int k = 0; k < FEF_NPREC; ++k) p->ops_bytes[k] = oOps[k];
+
+  // ---- pairs, work items, neighbours ----------------------------------------
+  p->npair = d->npair;
+  std::vector<PairInfo> pairs(d->npair);
+  std::vector<Item> items;
+  std::vector<std::vector<std::pair<int32_t, double>>> nbr(d->nfrag);
+  for (int64_t k = 0; k < d->npair; ++k) {
+    int32_t x = d->pair_x[k], y = d->pair_y[k];
+    const double s = d->pair_s[k];
+    if (x < 0 || y < 0 || x >= d->nfrag || y >= d->nfrag || x == y || !std::isfinite(s)) {
+      free_plan(p);
+      return FEF_E_SHAPE;
+    }
+    if (p->frag[y].cls != 0) {
+      if (p->frag[x].cls != 0) { free_plan(p); return FEF_E_SHAPE; }
+      std::swap(x, y);  // E2_xy = E2_yx; the class-0 fragment supplies B_ov
+    }
+    PairInfo& pi = pairs[k];
+    pi.x = x; pi.y = y; pi.s = s;
+    pi.item_first = (int32_t)items.size();
+    const FragInfo& fx = p->frag[x];
+    const FragInfo& fy = p->frag[y];
+    for (int mt = 0; mt < fx.ntile; ++mt)
+      for (int nt = 0; nt < fy.ntile; ++nt) items.push_back({(int32_t)k, mt, nt, 0});
+    pi.item_count = (int32_t)items.size() - pi.item_first;
+    nbr[x].push_back({y, s});
+    nbr[y].push_back({x, s});
+  }
+  if (items.size() > (size_t)INT32_MAX) { free_plan(p); return FEF_E_UNSUPPORTED; }
+  p->nitems = (int64_t)items.size();
+  std::vector<int32_t> nptr(d->nfrag + 1, 0), nidx;
+  std::vector<double> ns;
+  for (int f = 0; f < d->nfrag; ++f) {
+    auto& v = nbr[f];
+    std::sort(v.begin(), v.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    nptr[f + 1] = nptr[f] + (int32_t)v.size();
+    for (auto& e : v) { nidx.push_back(e.first); ns.push_back(e.second); }
+  }
+  p->nbr_total = (int64_t)nidx.size();
+
+  // ---- half-transform tasks and eigen-solver groups --------------------------
+  std::vector<HtTask> ht;
+  for (int f = 0; f < d->nfrag; ++f) {
+    const FragInfo& fi = p->frag[f];
+    if (fi.ov == 0) continue;
+    for (int p0 = 0; p0 < fi.naux; p0 += 8) ht.push_back({f, p0, std::min(8, fi.naux - p0), 0});
+  }
+  p->ht_ntasks = (int64_t)ht.size();
+  for (int f = 0; f < d->nfrag; ++f) {
+    const int n = p->frag[f].nbf;
+    if (n <= 32) p->eig_small.push_back(f);
+    else if (n <= 48) p->eig_mid.push_back(f);
+    else { p->eig_large.push_back(f); p->eig_large_max_nbf = std::max(p->eig_large_max_nbf, n); }
+  }
+
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = upload(&p->d_frag, p->frag);
+  if (e == hipSuccess) e = upload(&p->d_pair, pairs);
+  if (e == hipSuccess) e = upload(&p->d_item, items);
+  if (e == hipSuccess) e = upload(&p->d_ht, ht);
+  if (e == hipSuccess) e = upload(&p->d_off_G, p->off_G);
+  if (e == hipSuccess) e = upload(&p->d_naux_cls_off, p->naux_cls_off);
+  if (e == hipSuccess) e = upload(&p->d_nbr_ptr, nptr);
+  if (e == hipSuccess) e = upload(&p->d_nbr_idx, nidx);
+  if (e == hipSuccess) e = upload(&p->d_nbr_s, ns);
+  if (e == hipSuccess) e = upload(&p->d_eig_small, p->eig_small);
+  if (e == hipSuccess) e = upload(&p->d_eig_mid, p->eig_mid);
+  if (e == hipSuccess) e = upload(&p->d_eig_large, p->eig_large);
+  if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
+  *out = p;
+  return FEF_OK;
+}
+
+fef_status fef_plan_destroy(fef_plan p) {
+  if (!p) return FEF_E_ARG;
+  free_plan(p);
+  return FEF_OK;
+}
+
+fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* out) {
+  if (!p || !out) return FEF_E_ARG;
+  const bool needs_prec = what == FEF_Q_OPS_BYTES || what == FEF_Q_HALF_WS_BYTES ||
+                          what == FEF_Q_PAIR_WS_BYTES;
+  if (needs_prec && !valid_prec(prec)) return FEF_E_PREC;
+  switch (what) {
+    case FEF_Q_OPS_BYTES: *out = p->ops_bytes[prec]; break;
+    case FEF_Q_HALF_WS_BYTES: *out = half_ws_bytes(*p, prec); break;
+    case FEF_Q_PAIR_WS_BYTES: *out = pair_ws_bytes(*p, prec); break;
+    case FEF_Q_FIELD_WS_BYTES: *out = field_ws_bytes(*p); break;
+    case FEF_Q_SCF_WS_BYTES: *out = scf_ws_bytes(*p); break;
+    case FEF_Q_BOV_ELEMS: *out = p->nBov; break;
+    case FEF_Q_W_ELEMS: *out = p->nW; break;
+    case FEF_Q_NITEMS: *out = p->nitems; break;
+    case FEF_Q_B_ELEMS: *out = p->nB; break;
+    case FEF_Q_C_ELEMS: *out = p->nC; break;
+    case FEF_Q_EPS_ELEMS: *out = p->nEps; break;
+    case FEF_Q_G_ELEMS: *out = p->nG; break;
+    case FEF_Q_NPAIR: *out = p->npair; break;
+    default: return FEF_E_ARG;
+  }
+  return FEF_OK;
+}
+
+static fef_status hip_status(hipError_t e) { return e == hipSuccess ? FEF_OK : FEF_E_HIP; }
+
+fef_status fef_half_transform(fef_plan p, const double* B, const double* C, const double* G,
+                              double* Bov, double* W, void* ops, fef_prec prec, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (!valid_prec(prec)) return FEF_E_PREC;
+  if (p->nfrag > 0 && (!B || !C || !G || !ops)) return FEF_E_ARG;
+  if ((int64_t)ws_bytes < half_ws_bytes(*p, prec) || (!ws && ws_bytes)) return FEF_E_WORKSPACE;
+  if (p->nfrag == 0) return FEF_OK;
+  double* bov = Bov ? Bov : static_cast<double*>(ws);
+  double* w = W ? W : static_cast<double*>(ws) + p->nBov;
+  return hip_status(launch_half_transform(*p, B, C, G, bov, w, ops, prec,
+                                          static_cast<hipStream_t>(stream)));
+}
+
+fef_status fef_pair_energies(fef_plan p, const void* ops, const double* eps, fef_prec prec,
+                             double* E2_pair, double* E2_total, int32_t* flags, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (!valid_prec(prec)) return FEF_E_PREC;
+  if (!E2_total || !flags) return FEF_E_ARG;
+  if (p->npair > 0 && (!ops || !eps || !E2_pair)) return FEF_E_ARG;
+  if ((int64_t)ws_bytes < pair_ws_bytes(*p, prec) || !ws) return FEF_E_WORKSPACE;
+  return hip_status(launch_pair_energies(*p, ops, eps, prec, E2_pair, E2_total, flags, ws,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+fef_status fef_coulomb_field(fef_plan p, const double* B, const double* G, const double* D,
+                             double* J, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (p->nfrag > 0 && (!B || !G || !D || !J)) return FEF_E_ARG;
+  if ((int64_t)ws_bytes < field_ws_bytes(*p) || !ws) return FEF_E_WORKSPACE;
+  if (p->nfrag == 0) return FEF_OK;
+  double* wd = static_cast<double*>(ws);
+  double* wphi = wd + naux_total(*p);
+  return hip_status(launch_field(*p, B, G, D, nullptr, nullptr, J, wd, wphi,
+                                 static_cast<hipStream_t>(stream)));
+}
+
+fef_status fef_scf_step(fef_plan p, const double* B, const double* G, const double* F0,
+                        const double* htilde, double* C, double* eps, double* D,
+                        double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (!dD_max || !flags) return FEF_E_ARG;
+  if (p->nfrag > 0 && (!B || !G || !F0 || !C || !eps)) return FEF_E_ARG;
+  if ((int64_t)ws_bytes < scf_ws_bytes(*p) || !ws) return FEF_E_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* wd = static_cast<double*>(ws);
+  double* wphi = wd + naux_total(*p);
+  double* base = static_cast<double*>(ws) + field_ws_bytes(*p) / (int64_t)sizeof(double);
+  double* Dold = base;
+  double* F = Dold + std::max<int64_t>(p->nC, 1);
+  double* Dnew = D ? D : F + std::max<int64_t>(p->nC, 1);
+  double* eigws = F + 2 * std::max<int64_t>(p->nC, 1);
+  hipError_t e = launch_density(*p, C, Dold, dD_max, st);
+  if (e == hipSuccess && p->nfrag > 0)
+    e = launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
+  if (e == hipSuccess && p->nfrag > 0)
+    e = launch_eigh(*p, F, Dold, C, eps, Dnew, dD_max, flags, eigws, st);
+  return hip_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Effective Coulomb field of the polarisation-screened fragment Fock matrix
+// (the "bubble" integrals 2 v^{mu j}_{nu j} summed over every other fragment
+// inside the cutoff), through the factored integrals:
+//   D^y      = C^y_occ C^y_occ^T                     (density, no factor 2)
+//   d^y_Q    = sum_{lambda sigma} B^y[Q][lambda sigma] D^y[lambda sigma]
+//   phi^x    = sum_{y in nbr(x)} s_xy G_{c(x) c(y)} d^y
+//   J^x      = 2 sum_P B^x[P] phi^x_P ;  F~^x = F0^x + h~^x + J^x
+// Moments and J each stream B once (HBM bound); the neighbour sum gathers
+// P-vectors of the neighbours (L2 resident).
+#include "fef_internal.h"
+#include "fef_device.h"
+
+namespace fef {
+
+__global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict__ frag,
+                                                      const double* __restrict__ C,
+                                                      double* __restrict__ D,
+                                                      double* __restrict__ dD_max) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && dD_max) *dD_max = 0.0;
+  const FragInfo fi = frag[blockIdx.x];
+  const int n = fi.nbf, o = fi.nocc;
+  const double* c = C + fi.off_C;
+  double* d = D + fi.off_C;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int l = e / n, s = e - (e / n) * n;
+    double acc = 0.0;
+    for (int j = 0; j < o; ++j) acc = fma(c[l * n + j], c[s * n + j], acc);
+    d[e] = acc;
+  }
+}
+
+__global__ void zero_scalar_kernel(double* p) { *p = 0.0; }
+
+// d^x_Q: one wave per Q, four Q per block.
+__global__ __launch_bounds__(256) void moments_kernel(const FragInfo* __restrict__ frag,
+                                                      const double* __restrict__ B,
+                                                      const double* __restrict__ D,
+                                                      double* __restrict__ dmom) {
+  const FragInfo fi = frag[blockIdx.x];
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (q >= fi.naux) return;
+  const int lane = threadIdx.x & 63;
+  const int nn = fi.nbf * fi.nbf;
+  const double* b = B + fi.off_B + (int64_t)q * nn;
+  const double* d = D + fi.off_C;
+  double acc = 0.0;
+  for (int e = lane; e < nn; e += 64) acc = fma(b[e], d[e], acc);
+  acc = wave_sum(acc);
+  if (lane == 0) dmom[fi.off_aux + q] = acc;
+}
+
+// phi^x.  The neighbour moments are first summed per class,
+// e_c = sum_{y in nbr(x), c(y) = c} s_xy d^y (fixed neighbour order), then
+// phi^x = sum_c G_{c(x) c} e_c with G_{c,0} stored and G_{0,c} = G_{c,0}^T.
+__global__ __launch_bounds__(256) void field_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ nbr_ptr,
+    const int32_t* __restrict__ nbr_idx, const double* __restrict__ nbr_s,
+    const double* __restrict__ G, const int64_t* __restrict__ off_G, int P0, int nclass,
+    const int32_t* __restrict__ naux_cls_off, const double* __restrict__ dmom,
+    double* __restrict__ phi) {
+  extern __shared__ double e[];  // concatenated e_c, sum of P_c over classes
+  const int x = blockIdx.x;
+  const FragInfo fx = frag[x];
+  const int etot = naux_cls_off[nclass];
+  for (int t = threadIdx.x; t < etot; t += blockDim.x) e[t] = 0.0;
+  __syncthreads();
+  const int beg = nbr_ptr[x], end = nbr_ptr[x + 1];
+  for (int k = beg; k < end; ++k) {
+    const int y = nbr_idx[k];
+    const double s = nbr_s[k];
+    const FragInfo fy = frag[y];
+    const int base = naux_cls_off[fy.cls];
+    const double* dy = dmom + fy.off_aux;
+    for (int q = threadIdx.x; q < fy.naux; q += blockDim.x) e[base + q] = fma(s, dy[q], e[base + q]);
+  }
+  __syncthreads();
+  const int cx = fx.cls;
+  for (int p = threadIdx.x; p < fx.naux; p += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < nclass; ++c) {
+      const int pc = naux_cls_off[c + 1] - naux_cls_off[c];
+      const double* ec = e + naux_cls_off[c];
+      if (c == 0) {
+        const double* g = G + off_G[cx];  // G_{cx,0}: [P_cx][P0]
+        for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)p * P0 + q], ec[q], acc);
+      } else if (cx == 0) {
+        const double* g = G + off_G[c];   // G_{c,0}: [P_c][P0]; use its transpose
+        for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)q * P0 + p], ec[q], acc);
+      }
+    }
+    phi[fx.off_aux + p] = acc;
+  }
+}
+
+// out^x[mu nu] = (F0 + h~)[mu nu] + 2 sum_P B^x[P][mu nu] phi^x_P.
+__global__ __launch_bounds__(256) void jbuild_kernel(const FragInfo* __restrict__ frag,
+                                                     const double* __restrict__ B,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ F0,
+                                                     const double* __restrict__ htilde,
+                                                     double* __restrict__ out) {
+  const FragInfo fi = frag[blockIdx.x];
+  const int nn = fi.nbf * fi.nbf;
+  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  if (e >= nn) return;
+  const double* b = B + fi.off_B + e;
+  const double* ph = phi + fi.off_aux;
+  double acc = 0.0;
+  for (int P = 0; P < fi.naux; ++P) acc = fma(b[(int64_t)P * nn], ph[P], acc);
+  double v = 2.0 * acc;
+  if (F0) v += F0[fi.off_C + e];
+  if (htilde) v += htilde[fi.off_C + e];
+  out[fi.off_C + e] = v;
+}
+
+hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* dD_max,
+                          hipStream_t st) {
+  if (p.nfrag == 0) {
+    hipLaunchKernelGGL(zero_scalar_kernel, dim3(1), dim3(1), 0, st, dD_max);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(density_kernel, dim3(p.nfrag), dim3(256), 0, st, p.d_frag, C, D, dD_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G, const double* D,
+                        const double* F0, const double* htilde, double* out, double* ws_d,
+                        double* ws_phi, hipStream_t st) {
+  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 3) / 4), dim3(256), 0, st,
+                     p.d_frag, B, D, ws_d);
+  const int etot = p.naux_cls_off.back();
+  hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), etot * sizeof(double), st, p.d_frag,
+                     p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
+                     p.d_naux_cls_off, ws_d, ws_phi);
+  const int nnmax = p.max_nbf * p.max_nbf;
+  hipLaunchKernelGGL(jbuild_kernel, dim3(p.nfrag, (nnmax + 255) / 256), dim3(256), 0, st,
+                     p.d_frag, B, ws_phi, F0, htilde, out);
+  return hipGetLastError();
+}
+
+}  // namespace fef

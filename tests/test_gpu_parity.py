@@ -1,0 +1,186 @@
+"""GPU parity: every entry point of the HIP library against the CPU oracle on
+the same seeded inputs (element by element), plus properties that hold at any
+size.  FP64 bar: 1e-9 Eh per pair energy."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import fefgen
+from oracle import fef as ofef
+
+pytestmark = pytest.mark.gpu
+
+PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
+TOL_PAIR_F64 = 1e-9
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def ctx_for(sysm, **kw):
+    import paper_1708_03377_amd as lib
+    return lib.Context(sysm, **kw)
+
+
+def ragged_system(seed=21):
+    # odd ov (not multiples of 16), nocc = 1, nvir = 1, ov = 0 on either side,
+    # a two-tile fragment (ov = 161), P = 6 (padded to 8)
+    sizes = [(24, 5), (7, 3), (10, 1), (5, 4), (4, 4), (6, 0), (30, 7), (3, 1)]
+    return fefgen.make_random_system(seed, sizes, naux=6)
+
+
+def two_class_system(seed=22):
+    # a 300-wide (4-tile) solute of class 1 with P1 = 20 among P0 = 8 solvent fragments
+    return fefgen.make_two_class_system(seed, (40, 10, 20),
+                                        [(24, 5), (9, 2), (24, 5), (13, 6)], naux0=8)
+
+
+# ---------------------------------------------------------------------------
+def test_half_transform_matches_oracle(torch):
+    for sysm in (ragged_system(), two_class_system()):
+        _say("half transform", sysm.nfrag)
+        ctx = ctx_for(sysm)
+        bov = torch.zeros(max(ctx.sizes["bov"], 1), dtype=torch.float64, device="cuda")
+        w = torch.zeros(max(ctx.sizes["w"], 1), dtype=torch.float64, device="cuda")
+        ctx.half_transform(PREC["f64"], bov, w)
+        torch.cuda.synchronize()
+        bov = bov.cpu().numpy(); w = w.cpu().numpy()
+        ob = 0; ow = 0
+        P0 = int(sysm.naux_class[0])
+        for f in range(sysm.nfrag):
+            o = int(sysm.nocc[f]); n = int(sysm.nbf[f]); P = int(sysm.naux[f])
+            ov = o * (n - o)
+            ref = ofef.half_transform(sysm.B_of(f), sysm.C_of(f), o).reshape(P, ov)
+            got = bov[ob:ob + P * ov].reshape(P, ov)
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+            refw = sysm.G_of(int(sysm.cls[f])).T @ ref
+            gotw = w[ow:ow + P0 * ov].reshape(P0, ov)
+            np.testing.assert_allclose(gotw, refw, rtol=0, atol=1e-13)
+            ob += P * ov; ow += P0 * ov
+
+
+@pytest.mark.parametrize("which", ["ragged", "two_class", "config0"])
+def test_pair_energies_f64(torch, which):
+    sysm = {"ragged": ragged_system, "two_class": two_class_system,
+            "config0": lambda: fefgen.make_system(0)}[which]()
+    _say("pair energies f64", which, sysm.npair)
+    ref, ref_tot = ofef.pair_energies(sysm)
+    ctx = ctx_for(sysm)
+    E2, tot = ctx.energies(PREC["f64"])
+    torch.cuda.synchronize()
+    E2 = E2.cpu().numpy(); tot = float(tot.cpu()[0])
+    assert np.max(np.abs(E2 - ref)) <= TOL_PAIR_F64
+    assert abs(tot - ref_tot) <= TOL_PAIR_F64 * max(1, sysm.npair) ** 0.5
+    assert int(ctx.flags.cpu()[0]) == 0
+
+
+def test_zero_width_pairs_are_zero(torch):
+    sysm = ragged_system()
+    ctx = ctx_for(sysm)
+    E2, _ = ctx.energies(PREC["f64"])
+    E2 = E2.cpu().numpy()
+    ov = sysm.nocc * (sysm.nbf - sysm.nocc)
+    zero = (ov[sysm.pair_x] == 0) | (ov[sysm.pair_y] == 0)
+    assert zero.any()
+    assert np.all(E2[zero] == 0.0)
+    assert np.all(E2[~zero] < 0.0)
+
+
+def test_empty_pair_list(torch):
+    sysm = fefgen.make_random_system(3, [(6, 2), (5, 2)], naux=4)
+    sysm.pair_x = sysm.pair_x[:0]; sysm.pair_y = sysm.pair_y[:0]
+    sysm.pair_s = sysm.pair_s[:0]; sysm.pair_r = sysm.pair_r[:0]
+    ctx = ctx_for(sysm)
+    ctx.E2_total.fill_(123.0)
+    _, tot = ctx.energies(PREC["f64"])
+    assert float(tot.cpu()[0]) == 0.0
+
+
+def test_coulomb_field_matches_oracle(torch):
+    for sysm in (ragged_system(), two_class_system(), fefgen.make_system(0)):
+        _say("field", sysm.nfrag)
+        ctx = ctx_for(sysm)
+        Dl = ofef.densities(sysm)
+        D = torch.from_numpy(np.concatenate([d.ravel() for d in Dl])).cuda()
+        J = torch.zeros_like(D)
+        ctx.coulomb_field(D, J)
+        J = J.cpu().numpy()
+        ref = ofef.coulomb_field(sysm, Dl)
+        oc = sysm.off_C
+        for f in range(sysm.nfrag):
+            np.testing.assert_allclose(J[oc[f]:oc[f + 1]], ref[f].ravel(), rtol=0,
+                                       atol=1e-12 * max(1.0, np.max(np.abs(ref[f]))))
+
+
+@pytest.mark.parametrize("which,niter", [("config0", 3), ("ragged", 2), ("two_class", 2)])
+def test_scf_then_pair_energies(torch, which, niter):
+    sysm = {"ragged": ragged_system, "two_class": two_class_system,
+            "config0": lambda: fefgen.make_system(0)}[which]()
+    _say("scf", which, niter)
+    ctx = ctx_for(sysm)
+    C, e = sysm.C.copy(), sysm.eps.copy()
+    for it in range(niter):
+        dmax = float(ctx.scf_step().cpu()[0])
+        C, e, Dl, odmax, ok = ofef.scf_step(sysm, C, e)
+        assert abs(dmax - odmax) <= 1e-10
+        np.testing.assert_allclose(ctx.eps.cpu().numpy(), e, rtol=0, atol=1e-10)
+        D = ctx.D.cpu().numpy()
+        oc = sysm.off_C
+        for f in range(sysm.nfrag):
+            np.testing.assert_allclose(D[oc[f]:oc[f + 1]], Dl[f].ravel(), rtol=0, atol=1e-10)
+    ref, ref_tot = ofef.pair_energies(sysm, C, e)
+    E2, tot = ctx.energies(PREC["f64"])
+    E2 = E2.cpu().numpy()
+    assert np.max(np.abs(E2 - ref)) <= TOL_PAIR_F64
+
+
+def test_bitwise_repeatable_and_order_invariant(torch):
+    sysm = fefgen.make_system(0)
+    ctx = ctx_for(sysm)
+    a = ctx.energies(PREC["f64"])[0].cpu().numpy().copy()
+    b = ctx.energies(PREC["f64"])[0].cpu().numpy().copy()
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(0).permutation(sysm.npair)
+    s2 = fefgen.make_system(0)
+    s2.pair_x, s2.pair_y = s2.pair_y[perm].copy(), s2.pair_x[perm].copy()  # also swap x<->y
+    s2.pair_s = s2.pair_s[perm].copy(); s2.pair_r = s2.pair_r[perm].copy()
+    c = ctx_for(s2).energies(PREC["f64"])[0].cpu().numpy()
+    np.testing.assert_allclose(c, a[perm], rtol=1e-13, atol=0)
+
+
+def test_gap_and_nonfinite_flags(torch):
+    sysm = fefgen.make_random_system(4, [(6, 2), (5, 2), (6, 3)], naux=4)
+    o = sysm.off_eps
+    sysm.eps[o[1]:o[2]] = [-0.5, 0.2, 0.1, 0.4, 0.9]  # LUMO below HOMO on fragment 1
+    ctx = ctx_for(sysm)
+    ctx.energies(PREC["f64"])
+    assert int(ctx.flags.cpu()[0]) & 1
+    sysm2 = fefgen.make_random_system(4, [(6, 2), (5, 2), (6, 3)], naux=4)
+    sysm2.B[5] = np.nan
+    ctx2 = ctx_for(sysm2)
+    ctx2.energies(PREC["f64"])
+    assert int(ctx2.flags.cpu()[0]) & 2
+
+
+@pytest.mark.parametrize("prec,tol_pair", [("f32", 1e-5), ("bf16x2", 1e-5), ("fp16x2", 1e-6)])
+def test_reduced_precision_config0(torch, prec, tol_pair):
+    sysm = fefgen.make_system(0)
+    ref, ref_tot = ofef.pair_energies(sysm)
+    ctx = ctx_for(sysm)
+    E2, tot = ctx.energies(PREC[prec])
+    E2 = E2.cpu().numpy(); tot = float(tot.cpu()[0])
+    err = np.max(np.abs(E2 - ref))
+    _say(prec, "max pair err", err, "total err", tot - ref_tot)
+    assert err <= tol_pair

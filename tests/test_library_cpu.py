@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/fef.h, and rejects bad arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1708_03377_amd import _fef
+    if not os.path.exists(_fef.LIB_PATH):
+        pytest.fail("libfef.so is not built (run __graft_entry__.build())")
+    return _fef, _fef.load_library()
+
+
+def declared_entry_points():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w\*]+\s+\*?(fef_\w+)\s*\(", txt, re.M))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    F, lib = _lib()
+    names = declared_entry_points()
+    assert {"fef_half_transform", "fef_pair_energies", "fef_coulomb_field",
+            "fef_scf_step"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert names == set(F.ENTRY_POINTS)
+
+
+def test_status_strings():
+    F, lib = _lib()
+    assert F.fef_status_string(0) == "ok"
+    assert "workspace" in F.fef_status_string(F.FEF_E_WORKSPACE)
+    assert F.fef_status_string(-99) == "unknown status"
+
+
+def test_null_arguments_rejected():
+    F, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.fef_plan_create(None, ctypes.byref(h)) == F.FEF_E_ARG
+    out = ctypes.c_int64()
+    assert lib.fef_plan_query(None, 0, 0, ctypes.byref(out)) == F.FEF_E_ARG
+    assert lib.fef_half_transform(None, None, None, None, None, None, None, 0, None, 0,
+                                  None) == F.FEF_E_ARG
+    assert lib.fef_pair_energies(None, None, None, 0, None, None, None, None, 0,
+                                 None) == F.FEF_E_ARG
+    assert lib.fef_coulomb_field(None, None, None, None, None, None, 0, None) == F.FEF_E_ARG
+    assert lib.fef_scf_step(None, None, None, None, None, None, None, None, None, None, None,
+                            0, None) == F.FEF_E_ARG
+
+
+def test_bad_shapes_rejected_before_device():
+    import numpy as np
+    F, lib = _lib()
+
+    def desc(nbf, nocc, cls, naux):
+        arrs = [np.array(a, dtype=np.int32) for a in (nbf, nocc, cls, naux)]
+        d = F.SystemDesc(len(nbf), len(naux), *(a.ctypes.data for a in arrs), 0,
+                         None, None, None)
+        return d, arrs
+    h = ctypes.c_void_p()
+    for args in [([4], [5], [0], [3]),      # nocc > nbf
+                 ([4], [-1], [0], [3]),     # negative nocc
+                 ([4], [2], [1], [3]),      # class out of range
+                 ([4], [2], [0], [0]),      # zero factor rank
+                 ([0], [0], [0], [3])]:     # empty fragment
+        d, keep = desc(*args)
+        assert lib.fef_plan_create(ctypes.byref(d), ctypes.byref(h)) == F.FEF_E_SHAPE
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    from paper_1708_03377_amd import _fef
+    with pytest.raises(RuntimeError, match="missing"):
+        _fef.load_library(str(tmp_path / "libfef.so"))
