@@ -22,7 +22,7 @@
  * Integral model: (mu nu|lambda sigma)^{xy} = sum_PQ B^x_{P mu nu} T^{xy}_{PQ}
  * B^y_{Q lambda sigma} with T^{xy} = s_xy G_{c(x),c(y)}, s_xy = 1/R_xy
  * (bohr^-1) and G_{0,c} = G_{c,0}^T.  Class 0 is the solvent class; every
- * pair must contain at least one class-0 fragment.
+ * pair must contain at least one class-0 fragment, and P_0 <= 80.
  *
  * Conventions
  *   Units: Hartree and bohr.  Row-major throughout.  MO order within a
@@ -111,22 +111,37 @@ typedef enum {
   FEF_Q_SCF_WS_BYTES = 4,   /* workspace of fef_scf_step                 */
   FEF_Q_BOV_ELEMS = 5,      /* doubles in the dense Bov pool             */
   FEF_Q_W_ELEMS = 6,        /* doubles in the dense W pool               */
-  FEF_Q_NITEMS = 7,         /* pair-kernel work items                    */
+  FEF_Q_NITEMS = 7,         /* pair-kernel work items of mode `prec`     */
   FEF_Q_B_ELEMS = 8,        /* doubles in the B pool                     */
   FEF_Q_C_ELEMS = 9,        /* doubles in a C / D / F0 / J pool          */
   FEF_Q_EPS_ELEMS = 10,     /* doubles in the eps pool                   */
   FEF_Q_G_ELEMS = 11,       /* doubles in the G pool                     */
-  FEF_Q_NPAIR = 12
+  FEF_Q_NPAIR = 12,
+  FEF_Q_NSLOT = 13,         /* pair output tiles (partial-sum slots)     */
+  FEF_Q_NENTRIES = 14       /* streamed y tiles of mode `prec`'s tiling   */
 } fef_query;
 
-/* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES and
- * FEF_Q_PAIR_WS_BYTES; it is ignored otherwise. */
+/* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES,
+ * FEF_Q_PAIR_WS_BYTES, FEF_Q_NITEMS and FEF_Q_NENTRIES; it is ignored
+ * otherwise. */
 fef_status fef_plan_query(fef_plan plan, fef_query what, fef_prec prec,
                           int64_t* out);
 
+/* Pair-kernel tiling of mode `prec` (the work decomposition; results agree
+ * across tilings up to the rounding order of the in-tile sums, and are
+ * bitwise reproducible for a fixed tiling).
+ *   xb : x-side row tiles held by one workgroup (FP64/FP32: 1; split modes:
+ *        2 or 4), each y tile streamed through the workgroup serves all.
+ *   yc : y tiles per work item of the persistent queue (1..4096).
+ * Rebuilds device tables (allocates): call outside graph capture, with no
+ * pair-energy call of this plan in flight.  The autotuner uses this. */
+fef_status fef_plan_set_tiles(fef_plan plan, fef_prec prec, int32_t xb, int32_t yc);
+fef_status fef_plan_get_tiles(fef_plan plan, fef_prec prec, int32_t* xb, int32_t* yc);
+
 /* Half transform (the x-side half of the four-index AO->MO transform).
  *   B, C, G : input pools (device).
- *   Bov, W  : optional dense FP64 outputs (device, may be NULL).
+ *   Bov, W  : optional dense FP64 outputs (device); both or neither may
+ *             be NULL.
  *   ops     : opaque operand pool for fef_pair_energies in mode `prec`,
  *             FEF_Q_OPS_BYTES bytes (device, required).
  *   ws      : workspace of FEF_Q_HALF_WS_BYTES bytes. */

@@ -29,9 +29,11 @@ PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
 
 Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
+Q_NSLOT, Q_NENTRIES = 13, 14
 
 # every entry point declared in include/fef.h
 ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
+                "fef_plan_set_tiles", "fef_plan_get_tiles",
                 "fef_half_transform", "fef_pair_energies", "fef_coulomb_field",
                 "fef_scf_step", "fef_status_string")
 
@@ -68,6 +70,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_plan_create.argtypes = [ctypes.POINTER(SystemDesc), ctypes.POINTER(vp)]
     lib.fef_plan_destroy.argtypes = [vp]
     lib.fef_plan_query.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    lib.fef_plan_set_tiles.argtypes = [vp, i32, i32, i32]
+    lib.fef_plan_get_tiles.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.fef_half_transform.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.fef_pair_energies.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.fef_coulomb_field.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
@@ -151,6 +155,18 @@ def fef_plan_query(plan: Plan, what: int, prec: int = 0) -> int:
     _check("fef_plan_query", load_library().fef_plan_query(plan.handle, what, prec,
                                                            ctypes.byref(out)))
     return out.value
+
+
+def fef_plan_set_tiles(plan: Plan, prec: int, xb: int, yc: int):
+    _check("fef_plan_set_tiles", load_library().fef_plan_set_tiles(plan.handle, prec, xb, yc))
+
+
+def fef_plan_get_tiles(plan: Plan, prec: int):
+    xb, yc = ctypes.c_int32(), ctypes.c_int32()
+    _check("fef_plan_get_tiles", load_library().fef_plan_get_tiles(plan.handle, prec,
+                                                                   ctypes.byref(xb),
+                                                                   ctypes.byref(yc)))
+    return xb.value, yc.value
 
 
 def fef_half_transform(plan, B, C, G, Bov, W, ops, prec, ws, stream=None):

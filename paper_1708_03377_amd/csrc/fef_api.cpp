@@ -23,7 +23,9 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 
 void free_plan(fef_plan_s* p) {
   if (!p) return;
-  void* ptrs[] = {p->d_frag, p->d_pair, p->d_item, p->d_ht, p->d_off_G, p->d_naux_cls_off,
+  for (auto& t : p->tiles) free_tiles(t);
+  void* ptrs[] = {p->d_frag, p->d_pair, p->d_slot_pair, p->d_ht, p->d_ht_fused, p->d_ht_generic,
+                  p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
                   p->d_eig_mid, p->d_eig_large};
   for (void* q : ptrs)
@@ -33,10 +35,25 @@ void free_plan(fef_plan_s* p) {
 
 OpsGeom geom_of(int prec, int P0) {
   switch (prec) {
-    case FEF_F64: return {8, (int)round_up(P0, 4)};
-    case FEF_F32: return {4, (int)round_up(P0, 4)};
-    default: return {2, (int)round_up(3 * (int64_t)P0, 32)};
+    case FEF_F64: return {8, (int)round_up(P0, 4), 0};
+    case FEF_F32: return {4, (int)round_up(P0, 4), 0};
+    default: {
+      const int pw = (int)round_up(P0, 8);
+      return {2, (int)round_up(3 * (int64_t)pw, 32), pw};
+    }
   }
+}
+
+// operand block bytes of one fragment (one role)
+int64_t operand_bytes(const OpsGeom& g, int prec, int64_t ld) {
+  if (prec == FEF_F64 || prec == FEF_F32) return round_up((int64_t)g.kpad * ld * g.elem_bytes, 256);
+  return round_up(ld * (2 * g.pw + 8) * g.elem_bytes, 256);
+}
+
+// default pair-kernel tiling per mode: (x units per block, entries per item)
+void default_tiles(int prec, int& xb, int& yc) {
+  xb = (prec == FEF_F64 || prec == FEF_F32) ? 1 : 4;
+  yc = 16;
 }
 
 bool valid_prec(int prec) { return prec >= 0 && prec < FEF_NPREC; }
@@ -48,8 +65,12 @@ namespace fef {
 int64_t half_ws_bytes(const fef_plan_s& p, fef_prec) {
   return (p.nBov + p.nW) * (int64_t)sizeof(double) + 256;
 }
+// partial sums [nslot], the persistent queue head, per-fragment gaps [sum ld],
+// 256 block sums of the total
 int64_t pair_ws_bytes(const fef_plan_s& p, fef_prec) {
-  return round_up(std::max<int64_t>(p.nitems, 1) * (int64_t)sizeof(double), 256);
+  return round_up(std::max<int64_t>(p.nslot, 1) * (int64_t)sizeof(double), 256) + 256 +
+         round_up(round_up(std::max<int64_t>(p.nGap, 1), 32) * (int64_t)sizeof(double), 256) +
+         256 * (int64_t)sizeof(double);
 }
 static int64_t naux_total(const fef_plan_s& p) {
   int64_t t = 0;
@@ -60,8 +81,8 @@ int64_t field_ws_bytes(const fef_plan_s& p) {
   return round_up(2 * std::max<int64_t>(naux_total(p), 1) * (int64_t)sizeof(double), 256);
 }
 int64_t scf_ws_bytes(const fef_plan_s& p) {
-  const int64_t large =
-      2 * (int64_t)p.eig_large.size() * p.eig_large_max_nbf * p.eig_large_max_nbf;
+  const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
+  const int64_t large = 2 * (int64_t)p.eig_large.size() * slot;
   int64_t n = 3 * std::max<int64_t>(p.nC, 1) + large;
   return field_ws_bytes(p) + round_up(n * (int64_t)sizeof(double), 256);
 }
@@ -93,6 +114,7 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   if (d->npair > (int64_t)INT32_MAX) return FEF_E_UNSUPPORTED;
   for (int c = 0; c < d->nclass; ++c)
     if (d->naux[c] < 1) return FEF_E_SHAPE;
+  if (d->naux[0] > 80) return FEF_E_UNSUPPORTED;  // pair-kernel LDS / register staging bound
   for (int f = 0; f < d->nfrag; ++f) {
     if (d->nbf[f] < 1 || d->nocc[f] < 0 || d->nocc[f] > d->nbf[f]) return FEF_E_SHAPE;
     if (d->cls[f] < 0 || d->cls[f] >= d->nclass) return FEF_E_SHAPE;
@@ -113,10 +135,12 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   p->naux_cls_off.assign(d->nclass + 1, 0);
   for (int c = 0; c < d->nclass; ++c) p->naux_cls_off[c + 1] = p->naux_cls_off[c] + d->naux[c];
   for (int k = 0; k < FEF_NPREC; ++k) p->geom[k] = geom_of(k, p->P0);
+  configure_split_kernels(p->geom[FEF_BF16X2].pw);
+  configure_plain_kernels(p->geom[FEF_F64].kpad, p->geom[FEF_F32].kpad);
 
   // ---- fragment table -----------------------------------------------------
   p->frag.resize(d->nfrag);
-  int64_t oB = 0, oC = 0, oE = 0, oBov = 0, oW = 0, oAux = 0;
+  int64_t oB = 0, oC = 0, oE = 0, oBov = 0, oW = 0, oAux = 0, oGap = 0;
   int64_t oOps[FEF_NPREC];
   // the operand pool starts with two scale factors per fragment (left, right)
   p->ops_header = round_up(16 * (int64_t)std::max(d->nfrag, 1), 256);
@@ -138,8 +162,9 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     fi.off_bov = oBov; oBov += (int64_t)fi.naux * fi.ov;
     fi.off_w = oW;  oW += (int64_t)p->P0 * fi.ov;
     fi.off_aux = oAux; oAux += fi.naux;
+    fi.off_gap = oGap; oGap += fi.ld;
     for (int k = 0; k < FEF_NPREC; ++k) {
-      const int64_t blk = round_up((int64_t)p->geom[k].kpad * fi.ld * p->geom[k].elem_bytes, 256);
+      const int64_t blk = operand_bytes(p->geom[k], k, fi.ld);
       fi.off_L[k] = oOps[k];
       oOps[k] += blk;
       if (fi.cls == 0) { fi.off_R[k] = oOps[k]; oOps[k] += blk; }
@@ -150,38 +175,34 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     p->max_ov = std::max(p->max_ov, fi.ov);
     p->max_on = std::max<int64_t>(p->max_on, (int64_t)fi.nocc * fi.nbf);
   }
-  p->nB = oB; p->nC = oC; p->nEps = oE; p->nBov = oBov; p->nW = oW;
+  p->nB = oB; p->nC = oC; p->nEps = oE; p->nBov = oBov; p->nW = oW; p->nGap = oGap;
   for (int k = 0; k < FEF_NPREC; ++k) p->ops_bytes[k] = oOps[k];
 
-  // ---- pairs, work items, neighbours ----------------------------------------
+  // ---- pairs, neighbours ---------------------------------------------------
   p->npair = d->npair;
-  std::vector<PairInfo> pairs(d->npair);
-  std::vector<Item> items;
+  p->pairs.resize(d->npair);
   std::vector<std::vector<std::pair<int32_t, double>>> nbr(d->nfrag);
   for (int64_t k = 0; k < d->npair; ++k) {
-    int32_t x = d->pair_x[k], y = d->pair_y[k];
+    const int32_t x = d->pair_x[k], y = d->pair_y[k];
     const double s = d->pair_s[k];
     if (x < 0 || y < 0 || x >= d->nfrag || y >= d->nfrag || x == y || !std::isfinite(s)) {
       free_plan(p);
       return FEF_E_SHAPE;
     }
-    if (p->frag[y].cls != 0) {
-      if (p->frag[x].cls != 0) { free_plan(p); return FEF_E_SHAPE; }
-      std::swap(x, y);  // E2_xy = E2_yx; the class-0 fragment supplies B_ov
-    }
-    PairInfo& pi = pairs[k];
+    if (p->frag[x].cls != 0 && p->frag[y].cls != 0) { free_plan(p); return FEF_E_SHAPE; }
+    PairInfo& pi = p->pairs[k];
+    std::memset(&pi, 0, sizeof(pi));
     pi.x = x; pi.y = y; pi.s = s;
-    pi.item_first = (int32_t)items.size();
-    const FragInfo& fx = p->frag[x];
-    const FragInfo& fy = p->frag[y];
-    for (int mt = 0; mt < fx.ntile; ++mt)
-      for (int nt = 0; nt < fy.ntile; ++nt) items.push_back({(int32_t)k, mt, nt, 0});
-    pi.item_count = (int32_t)items.size() - pi.item_first;
     nbr[x].push_back({y, s});
     nbr[y].push_back({x, s});
   }
-  if (items.size() > (size_t)INT32_MAX) { free_plan(p); return FEF_E_UNSUPPORTED; }
-  p->nitems = (int64_t)items.size();
+  order_and_orient(*p);
+  if (p->nslot > (int64_t)INT32_MAX) { free_plan(p); return FEF_E_UNSUPPORTED; }
+  std::vector<int32_t> slot_pair(p->nslot);
+  for (int64_t k = 0; k < d->npair; ++k) {
+    const PairInfo& pi = p->pairs[k];
+    for (int t = 0; t < pi.ntx * pi.nty; ++t) slot_pair[pi.slot_first + t] = (int32_t)k;
+  }
   std::vector<int32_t> nptr(d->nfrag + 1, 0), nidx;
   std::vector<double> ns;
   for (int f = 0; f < d->nfrag; ++f) {
@@ -193,13 +214,27 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   p->nbr_total = (int64_t)nidx.size();
 
   // ---- half-transform tasks and eigen-solver groups --------------------------
+  // small fragments take the fused half transform, the rest the generic chain
   std::vector<HtTask> ht;
+  int64_t mx_nn = 1, mx_on = 1, mx_pov = 1;
   for (int f = 0; f < d->nfrag; ++f) {
     const FragInfo& fi = p->frag[f];
     if (fi.ov == 0) continue;
+    if (fi.nbf <= 32 && fi.ntile == 1 && fi.naux <= 80) {
+      p->ht_fused.push_back(f);
+      p->max_naux_small = std::max(p->max_naux_small, fi.naux);
+      mx_nn = std::max<int64_t>(mx_nn, (int64_t)fi.nbf * fi.nbf);
+      mx_on = std::max<int64_t>(mx_on, (int64_t)fi.nocc * fi.nbf);
+      mx_pov = std::max<int64_t>(mx_pov, (int64_t)fi.naux * fi.ov);
+      continue;
+    }
+    p->ht_generic.push_back(f);
     for (int p0 = 0; p0 < fi.naux; p0 += 8) ht.push_back({f, p0, std::min(8, fi.naux - p0), 0});
   }
   p->ht_ntasks = (int64_t)ht.size();
+  p->fuse_lds[0] = (int32_t)mx_nn;   // largest nbf^2 among small fragments
+  p->fuse_lds[1] = (int32_t)mx_on;   // largest nocc * nbf
+  p->fuse_lds[2] = (int32_t)mx_pov;  // largest P_c * ov
   for (int f = 0; f < d->nfrag; ++f) {
     const int n = p->frag[f].nbf;
     if (n <= 32) p->eig_small.push_back(f);
@@ -209,9 +244,16 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
 
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(&p->d_frag, p->frag);
-  if (e == hipSuccess) e = upload(&p->d_pair, pairs);
-  if (e == hipSuccess) e = upload(&p->d_item, items);
+  if (e == hipSuccess) e = upload(&p->d_pair, p->pairs);
+  if (e == hipSuccess) e = upload(&p->d_slot_pair, slot_pair);
+  for (int k = 0; k < FEF_NPREC && e == hipSuccess; ++k) {
+    int xb, yc;
+    default_tiles(k, xb, yc);
+    e = build_tiles(*p, k, xb, yc);
+  }
   if (e == hipSuccess) e = upload(&p->d_ht, ht);
+  if (e == hipSuccess) e = upload(&p->d_ht_fused, p->ht_fused);
+  if (e == hipSuccess) e = upload(&p->d_ht_generic, p->ht_generic);
   if (e == hipSuccess) e = upload(&p->d_off_G, p->off_G);
   if (e == hipSuccess) e = upload(&p->d_naux_cls_off, p->naux_cls_off);
   if (e == hipSuccess) e = upload(&p->d_nbr_ptr, nptr);
@@ -234,7 +276,8 @@ fef_status fef_plan_destroy(fef_plan p) {
 fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* out) {
   if (!p || !out) return FEF_E_ARG;
   const bool needs_prec = what == FEF_Q_OPS_BYTES || what == FEF_Q_HALF_WS_BYTES ||
-                          what == FEF_Q_PAIR_WS_BYTES;
+                          what == FEF_Q_PAIR_WS_BYTES || what == FEF_Q_NITEMS ||
+                          what == FEF_Q_NENTRIES;
   if (needs_prec && !valid_prec(prec)) return FEF_E_PREC;
   switch (what) {
     case FEF_Q_OPS_BYTES: *out = p->ops_bytes[prec]; break;
@@ -244,18 +287,37 @@ fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* ou
     case FEF_Q_SCF_WS_BYTES: *out = scf_ws_bytes(*p); break;
     case FEF_Q_BOV_ELEMS: *out = p->nBov; break;
     case FEF_Q_W_ELEMS: *out = p->nW; break;
-    case FEF_Q_NITEMS: *out = p->nitems; break;
+    case FEF_Q_NITEMS: *out = p->tiles[prec].nitems; break;
     case FEF_Q_B_ELEMS: *out = p->nB; break;
     case FEF_Q_C_ELEMS: *out = p->nC; break;
     case FEF_Q_EPS_ELEMS: *out = p->nEps; break;
     case FEF_Q_G_ELEMS: *out = p->nG; break;
     case FEF_Q_NPAIR: *out = p->npair; break;
+    case FEF_Q_NSLOT: *out = p->nslot; break;
+    case FEF_Q_NENTRIES: *out = p->tiles[prec].nentries; break;
     default: return FEF_E_ARG;
   }
   return FEF_OK;
 }
 
 static fef_status hip_status(hipError_t e) { return e == hipSuccess ? FEF_OK : FEF_E_HIP; }
+
+fef_status fef_plan_set_tiles(fef_plan p, fef_prec prec, int32_t xb, int32_t yc) {
+  if (!p) return FEF_E_ARG;
+  if (!valid_prec(prec)) return FEF_E_PREC;
+  const bool plain = prec == FEF_F64 || prec == FEF_F32;
+  if (plain ? xb != 1 : (xb != 2 && xb != 4)) return FEF_E_UNSUPPORTED;
+  if (yc < 1 || yc > 4096) return FEF_E_ARG;
+  return hip_status(build_tiles(*p, prec, xb, yc));
+}
+
+fef_status fef_plan_get_tiles(fef_plan p, fef_prec prec, int32_t* xb, int32_t* yc) {
+  if (!p || !xb || !yc) return FEF_E_ARG;
+  if (!valid_prec(prec)) return FEF_E_PREC;
+  *xb = p->tiles[prec].xb;
+  *yc = p->tiles[prec].yc;
+  return FEF_OK;
+}
 
 fef_status fef_half_transform(fef_plan p, const double* B, const double* C, const double* G,
                               double* Bov, double* W, void* ops, fef_prec prec, void* ws,
@@ -265,10 +327,11 @@ fef_status fef_half_transform(fef_plan p, const double* B, const double* C, cons
   if (p->nfrag > 0 && (!B || !C || !G || !ops)) return FEF_E_ARG;
   if ((int64_t)ws_bytes < half_ws_bytes(*p, prec) || (!ws && ws_bytes)) return FEF_E_WORKSPACE;
   if (p->nfrag == 0) return FEF_OK;
+  if ((Bov == nullptr) != (W == nullptr)) return FEF_E_ARG;
   double* bov = Bov ? Bov : static_cast<double*>(ws);
   double* w = W ? W : static_cast<double*>(ws) + p->nBov;
   return hip_status(launch_half_transform(*p, B, C, G, bov, w, ops, prec,
-                                          static_cast<hipStream_t>(stream)));
+                                          static_cast<hipStream_t>(stream), Bov != nullptr));
 }
 
 fef_status fef_pair_energies(fef_plan p, const void* ops, const double* eps, fef_prec prec,

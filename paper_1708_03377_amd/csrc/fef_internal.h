@@ -13,6 +13,8 @@ namespace fef {
 // Pair-kernel output tile (rows = ia of x, columns = jb of y).  96 = 6 x 16
 // MFMA tiles, so a water-like fragment (ov = 95) needs one tile per side.
 constexpr int kTile = 96;
+// Largest number of x-side row tiles ("x units") one pair-kernel block holds.
+constexpr int kMaxXB = 4;
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
@@ -21,24 +23,39 @@ struct FragInfo {
   int32_t nbf, nocc, nvir, ov;
   int32_t cls, naux;     // class and its factor rank P_c
   int32_t ntile;         // ceil(ov / kTile)
-  int32_t pad0;
+  int32_t rank;          // position in the locality (RCM) order
   int64_t off_B, off_C, off_eps;
   int64_t off_bov, off_w;            // dense FP64 Bov / W pools
   int64_t off_aux;                   // offset into per-fragment [P_c] vectors
+  int64_t off_gap;                   // offset into the gap pool [ld] (Delta_ia, -1 padded)
   int64_t ld;                        // ntile * kTile
   int64_t off_L[FEF_NPREC];          // byte offsets of the left operand
   int64_t off_R[FEF_NPREC];          // byte offsets of the right operand (-1: none)
 };
 
-// Oriented pair: y is always a class-0 fragment.
+// Oriented pair: y is always a class-0 fragment.  Its (mt, nt) output tiles
+// own the partial-sum slots slot_first + mt * nty + nt.
 struct PairInfo {
   int32_t x, y;
   double s;
-  int32_t item_first, item_count;
+  int32_t slot_first, ntx, nty, pad;
 };
 
-struct Item {
-  int32_t pair, mt, nt, pad;
+// Pair-kernel work decomposition: an x-block holds up to kMaxXB x units
+// (fragment, row tile); its entries list every streamed y tile (fragment,
+// column tile) that pairs with at least one unit, with the unit's partial
+// slot (-1: no pair).  A work item is a contiguous range of one block's
+// entries.
+struct XBlock {
+  int32_t f[kMaxXB];
+  int32_t mt[kMaxXB];
+};
+struct Entry {
+  int32_t y, nt;
+  int32_t slot[kMaxXB];
+};
+struct WorkItem {
+  int32_t xblock, e0, ne, pad;
 };
 
 struct HtTask {
@@ -46,9 +63,23 @@ struct HtTask {
 };
 
 // Operand geometry of a precision mode.
+//   FP64 / FP32: operand stored [kpad][ld], k-major, kpad = round_up(P0, 4).
+//   split modes: operand stored [ld][2 * pw + 8] (row = ia; hi plane, lo
+//   plane, pw = round_up(P0, 8), then 8 zeros so that rows staged in LDS sit
+//   12 banks apart); the contraction runs over the concatenated axis of
+//   length kpad = round_up(3 * pw, 32).
 struct OpsGeom {
-  int elem_bytes;   // bytes per stored element (per plane for split modes)
+  int elem_bytes;   // bytes per stored element
   int kpad;         // padded contraction length
+  int pw;           // plane width (split modes)
+};
+
+struct TileSet {
+  int32_t xb = 0, yc = 0;
+  int64_t nitems = 0, nentries = 0, nxblocks = 0;
+  WorkItem* d_items = nullptr;
+  Entry* d_entries = nullptr;
+  XBlock* d_xblocks = nullptr;
 };
 
 }  // namespace fef
@@ -56,7 +87,7 @@ struct OpsGeom {
 struct fef_plan_s {
   int device = 0;
   int32_t nfrag = 0, nclass = 0, P0 = 0;
-  int64_t npair = 0, nitems = 0;
+  int64_t npair = 0, nslot = 0;
   int32_t max_nbf = 0, max_naux = 0, max_ov = 0;
   int64_t max_on = 0;   // max nocc * nbf (half-transform LDS)
   int64_t ops_header = 0;  // bytes of per-fragment scale factors at the start of ops
@@ -64,17 +95,25 @@ struct fef_plan_s {
   std::vector<int32_t> naux_cls;
   std::vector<int64_t> off_G;
   std::vector<int32_t> naux_cls_off;  // prefix sums of P_c over classes
-  int64_t nB = 0, nC = 0, nEps = 0, nBov = 0, nW = 0, nG = 0;
+  int64_t nB = 0, nC = 0, nEps = 0, nBov = 0, nW = 0, nG = 0, nGap = 0;
   int64_t ops_bytes[FEF_NPREC] = {0, 0, 0, 0};
   fef::OpsGeom geom[FEF_NPREC];
   // eigen-solver groups: fragments by size class
   std::vector<int32_t> eig_small, eig_mid, eig_large;
   int32_t eig_large_max_nbf = 0;
   int64_t ht_ntasks = 0;
+  std::vector<int32_t> ht_fused, ht_generic;  // half-transform paths per fragment
+  int32_t fuse_lds[3] = {0, 0, 0};             // small-fragment maxima: nbf^2, nocc nbf, P ov
+  int32_t max_naux_small = 0;                  // largest P_c among the small fragments
+  int32_t* d_ht_fused = nullptr;
+  int32_t* d_ht_generic = nullptr;
   // device tables
   fef::FragInfo* d_frag = nullptr;
   fef::PairInfo* d_pair = nullptr;
-  fef::Item* d_item = nullptr;
+  int32_t* d_slot_pair = nullptr;     // slot -> pair index
+  std::vector<fef::PairInfo> pairs;   // host copy (oriented)
+  std::vector<int32_t> rank;          // locality order position per fragment
+  fef::TileSet tiles[FEF_NPREC];
   fef::HtTask* d_ht = nullptr;
   int64_t* d_off_G = nullptr;
   int32_t* d_naux_cls_off = nullptr;
@@ -92,7 +131,7 @@ namespace fef {
 // Kernel launchers (defined next to their kernels).
 hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const double* C,
                                  const double* G, double* bov, double* w, void* ops,
-                                 fef_prec prec, hipStream_t st);
+                                 fef_prec prec, hipStream_t st, bool dense_out);
 hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const double* w,
                              void* ops, fef_prec prec, hipStream_t st);
 hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const double* eps,
@@ -106,6 +145,15 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* C, double* eps, double* Dnew, double* dD_max,
                        int32_t* flags, double* ws_eig, hipStream_t st);
+
+// Pair-kernel tiling (fef_tiles.cpp).
+void order_and_orient(fef_plan_s& p);
+hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc);
+void free_tiles(fef::TileSet& t);
+
+// One-time kernel attributes (dynamic LDS above 64 KB).
+void configure_split_kernels(int pw);
+void configure_plain_kernels(int kpad64, int kpad32);
 
 // Workspace sizes (bytes).
 int64_t half_ws_bytes(const fef_plan_s& p, fef_prec prec);

@@ -11,19 +11,55 @@
 //   c = 1 / sqrt(1 + t^2),  s = t c.
 // Sweeps stop when ||offdiag(A)||_F <= 1e-14 ||diag(A)||_2 (at most 40).
 // One workgroup per matrix; the matrix and eigenvectors live in LDS for
-// n <= 48 and in a global workspace slot otherwise.
+// n <= 48 and in a global workspace slot otherwise.  Each round makes two
+// passes: the rotation table, then every 2x2 block of A (rows of one pair,
+// columns of another: A_blk <- R_k^T A_blk R_l) together with V <- V J.
 #include "fef_internal.h"
 #include "fef_device.h"
 
 namespace fef {
 
+// Rotation (c, s) that zeroes a_pq of the 2x2 block [[a_pp, a_pq], [a_pq, a_qq]]
+// (classical symmetric Schur step).  Reciprocal and reciprocal square root
+// come from the hardware approximations refined by one Newton step each
+// (relative error ~1e-16); the rotation only has to zero a_pq to rounding
+// level, while c^2 + s^2 = 1 holds to rounding because s = t c exactly.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsq_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
+__device__ inline void jacobi_rotation(double app, double aqq, double apq, double& c, double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (apq == 0.0) return;
+  const double tau = (aqq - app) * 0.5 * rcp_nr(apq);
+  double t;
+  if (fabs(tau) > 1e150) {
+    t = 0.5 * rcp_nr(tau);
+  } else {
+    const double q = 1.0 + tau * tau;
+    const double sq = q * rsq_nr(q);  // sqrt(1 + tau^2)
+    t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + sq);
+  }
+  c = rsq_nr(1.0 + t * t);
+  s = t * c;
+}
+
+// Pair k of round r in the circle ordering of m (even) indices, p < q.
 __device__ inline void round_robin_pair(int r, int k, int m, int& p, int& q) {
+  const int m1 = m - 1;
   if (k == 0) {
     p = r;
-    q = m - 1;
+    q = m1;
   } else {
-    p = (r + k) % (m - 1);
-    q = (r - k + m - 1) % (m - 1);
+    p = r + k;
+    if (p >= m1) p -= m1;
+    q = r - k;
+    if (q < 0) q += m1;
   }
   if (p > q) {
     const int t = p;
@@ -32,42 +68,88 @@ __device__ inline void round_robin_pair(int r, int k, int m, int& p, int& q) {
   }
 }
 
-template <int NT, bool kLds>
+// kNmax > 0: matrices up to kNmax, held in LDS with stride kNmax + 1, index
+// decode by constant divisors, warm start from the input orbitals.
+// kNmax == 0: any size, matrices in a global workspace slot with stride m,
+// cold start from the identity.
+//
+// Warm start: with C the input orbitals (orthonormal columns), the solver
+// diagonalises A = C^T F C and accumulates V = C J_1 J_2 ..., so V ends as the
+// eigenvectors of F in the AO basis.  Near self-consistency A is nearly
+// diagonal and fewer sweeps are needed; the spectrum is the same for any
+// orthonormal C.
+template <int NT, int kNmax>
 __global__ __launch_bounds__(NT) void eigh_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
     const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
     double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
     int32_t* __restrict__ flags, double* __restrict__ ws_eig, int max_n) {
+  constexpr bool kLds = kNmax > 0;
+  constexpr int kH = kNmax / 2;
+  constexpr int kNB = kLds ? (kH * kH + NT - 1) / NT : 1;       // blocks per thread
+  constexpr int kNV = kLds ? (kNmax * kH + NT - 1) / NT : 1;    // V pairs per thread
   extern __shared__ double sm[];
   __shared__ double red[NT / 64];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int n = fi.nbf;
-  const int m = n + (n & 1);
+  const int m = n + (n & 1);  // an odd n gets a dummy index n (zero row/column)
   const int half = m / 2;
-  const int lda = kLds ? n + 1 : n;  // odd stride in LDS spreads the banks
+  const int lda = kLds ? kNmax + 1 : m;
   double *A, *V, *cs;
   if (kLds) {
     A = sm;
-    V = sm + (size_t)max_n * (max_n + 1);
-    cs = V + (size_t)max_n * (max_n + 1);
+    V = sm + kNmax * (kNmax + 1);
+    cs = V + kNmax * (kNmax + 1);
   } else {
-    A = ws_eig + (size_t)blockIdx.x * 2 * max_n * max_n;
-    V = A + (size_t)max_n * max_n;
+    const size_t slot = (size_t)(max_n + 1) * (max_n + 1);
+    A = ws_eig + (size_t)blockIdx.x * 2 * slot;
+    V = A + slot;
     cs = sm;
   }
   double* cc = cs;
   double* ss = cs + half;
-  int* rank = reinterpret_cast<int*>(ss + half);
-  double* lam = reinterpret_cast<double*>(rank + ((n + 1) & ~1));
+  int* pp = reinterpret_cast<int*>(ss + half);
+  int* qq = pp + half;
+  int* rank = qq + half;
+  double* lam = reinterpret_cast<double*>(rank + 2 * ((n + 1) / 2));
+  double* T = lam + (n + 1);  // warm-start scratch (LDS path), [kNmax][kNmax + 1]
 
   const double* Fx = F + fi.off_C;
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int i = e / n, j = e - (e / n) * n;
-    A[i * lda + j] = 0.5 * (Fx[i * n + j] + Fx[j * n + i]);
-    V[i * lda + j] = (i == j) ? 1.0 : 0.0;
+  const double* Cx = C + fi.off_C;
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const int i = e / m, j = e - (e / m) * m;
+    const bool in = i < n && j < n;
+    A[i * lda + j] = in ? 0.5 * (Fx[i * n + j] + Fx[j * n + i]) : 0.0;
+    V[i * lda + j] = kLds ? (in ? Cx[i * n + j] : 0.0) : ((in && i == j) ? 1.0 : 0.0);
   }
   __syncthreads();
+  if (kLds) {
+    // T = F C, then A = C^T T
+    for (int e = threadIdx.x; e < n * n; e += NT) {
+      const int i = e / n, j = e - (e / n) * n;
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc = fma(A[i * lda + k], V[k * lda + j], acc);
+      T[i * lda + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += NT) {
+      const int i = e / n, j = e - (e / n) * n;
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc = fma(V[k * lda + i], T[k * lda + j], acc);
+      A[i * lda + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += NT) {  // exact symmetry
+      const int i = e / n, j = e - (e / n) * n;
+      if (i < j) {
+        const double a = 0.5 * (A[i * lda + j] + A[j * lda + i]);
+        A[i * lda + j] = a;
+        A[j * lda + i] = a;
+      }
+    }
+    __syncthreads();
+  }
 
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
@@ -83,45 +165,99 @@ __global__ __launch_bounds__(NT) void eigh_kernel(
       for (int k = threadIdx.x; k < half; k += NT) {
         int p, q;
         round_robin_pair(r, k, m, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p * lda + q];
-          if (apq != 0.0) {
-            const double tau = (A[q * lda + q] - A[p * lda + p]) / (2.0 * apq);
-            double t;
-            if (fabs(tau) > 1e150) t = 0.5 / tau;
-            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
+        double c, s;
+        jacobi_rotation(A[p * lda + p], A[q * lda + q], A[p * lda + q], c, s);
         cc[k] = c;
         ss[k] = s;
+        pp[k] = p;
+        qq[k] = q;
       }
       __syncthreads();
-      for (int e = threadIdx.x; e < half * n; e += NT) {  // rows p, q of A
-        const int k = e / n, j = e - (e / n) * n;
-        int p, q;
-        round_robin_pair(r, k, m, p, q);
-        if (q >= n) continue;
-        const double c = cc[k], s = ss[k];
-        const double ap = A[p * lda + j], aq = A[q * lda + j];
-        A[p * lda + j] = c * ap - s * aq;
-        A[q * lda + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < half * n; e += NT) {  // columns p, q of A and V
-        const int k = e / n, i = e - (e / n) * n;
-        int p, q;
-        round_robin_pair(r, k, m, p, q);
-        if (q >= n) continue;
-        const double c = cc[k], s = ss[k];
-        const double ap = A[i * lda + p], aq = A[i * lda + q];
-        A[i * lda + p] = c * ap - s * aq;
-        A[i * lda + q] = s * ap + c * aq;
-        const double vp = V[i * lda + p], vq = V[i * lda + q];
-        V[i * lda + p] = c * vp - s * vq;
-        V[i * lda + q] = s * vp + c * vq;
+      if (kLds) {
+        // every 2x2 block (rows of pair k, columns of pair l) and every V
+        // row pair: all loads first, then the arithmetic, then all stores
+        double mb[kNB][4], vb[kNV][2];
+        int ab[kNB][4], av[kNV][2];
+        double cb[kNB][4], cv[kNV][2];
+        bool ok[kNB], okv[kNV];
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) {
+          const int b = threadIdx.x + NT * u;
+          const int k = b / kH, l = b - (b / kH) * kH;
+          ok[u] = b < kH * kH && k < half && l < half;
+          const int a0 = ok[u] ? pp[k] : 0, a1 = ok[u] ? qq[k] : 0;
+          const int b0 = ok[u] ? pp[l] : 0, b1 = ok[u] ? qq[l] : 0;
+          ab[u][0] = a0 * lda + b0; ab[u][1] = a0 * lda + b1;
+          ab[u][2] = a1 * lda + b0; ab[u][3] = a1 * lda + b1;
+          cb[u][0] = ok[u] ? cc[k] : 1.0; cb[u][1] = ok[u] ? ss[k] : 0.0;
+          cb[u][2] = ok[u] ? cc[l] : 1.0; cb[u][3] = ok[u] ? ss[l] : 0.0;
+#pragma unroll
+          for (int z = 0; z < 4; ++z) mb[u][z] = A[ab[u][z]];
+        }
+#pragma unroll
+        for (int u = 0; u < kNV; ++u) {
+          const int e = threadIdx.x + NT * u;
+          const int l = e / kNmax, i = e - (e / kNmax) * kNmax;
+          okv[u] = e < kNmax * kH && i < n && l < half;
+          const int p = okv[u] ? pp[l] : 0, q = okv[u] ? qq[l] : 0;
+          const int row = okv[u] ? i : 0;
+          av[u][0] = row * lda + p;
+          av[u][1] = row * lda + q;
+          cv[u][0] = okv[u] ? cc[l] : 1.0;
+          cv[u][1] = okv[u] ? ss[l] : 0.0;
+          vb[u][0] = V[av[u][0]];
+          vb[u][1] = V[av[u][1]];
+        }
+#pragma unroll
+        for (int u = 0; u < kNB; ++u) {
+          const double ck = cb[u][0], sk = cb[u][1], cl = cb[u][2], sl = cb[u][3];
+          const double t00 = ck * mb[u][0] - sk * mb[u][2], t01 = ck * mb[u][1] - sk * mb[u][3];
+          const double t10 = sk * mb[u][0] + ck * mb[u][2], t11 = sk * mb[u][1] + ck * mb[u][3];
+          mb[u][0] = cl * t00 - sl * t01;
+          mb[u][1] = sl * t00 + cl * t01;
+          mb[u][2] = cl * t10 - sl * t11;
+          mb[u][3] = sl * t10 + cl * t11;
+        }
+#pragma unroll
+        for (int u = 0; u < kNV; ++u) {
+          const double c = cv[u][0], s = cv[u][1], vp = vb[u][0], vq = vb[u][1];
+          vb[u][0] = c * vp - s * vq;
+          vb[u][1] = s * vp + c * vq;
+        }
+#pragma unroll
+        for (int u = 0; u < kNB; ++u)
+          if (ok[u]) {
+#pragma unroll
+            for (int z = 0; z < 4; ++z) A[ab[u][z]] = mb[u][z];
+          }
+#pragma unroll
+        for (int u = 0; u < kNV; ++u)
+          if (okv[u]) {
+            V[av[u][0]] = vb[u][0];
+            V[av[u][1]] = vb[u][1];
+          }
+      } else {
+        for (int b = threadIdx.x; b < half * half; b += NT) {
+          const int k = b / half, l = b - (b / half) * half;
+          const int a = pp[k], bb = qq[k], c = pp[l], d = qq[l];
+          const double ck = cc[k], sk = ss[k], cl = cc[l], sl = ss[l];
+          const double m00 = A[a * lda + c], m01 = A[a * lda + d];
+          const double m10 = A[bb * lda + c], m11 = A[bb * lda + d];
+          const double t00 = ck * m00 - sk * m10, t01 = ck * m01 - sk * m11;
+          const double t10 = sk * m00 + ck * m10, t11 = sk * m01 + ck * m11;
+          A[a * lda + c] = cl * t00 - sl * t01;
+          A[a * lda + d] = sl * t00 + cl * t01;
+          A[bb * lda + c] = cl * t10 - sl * t11;
+          A[bb * lda + d] = sl * t10 + cl * t11;
+        }
+        for (int e = threadIdx.x; e < n * half; e += NT) {
+          const int l = e / n, i = e - (e / n) * n;
+          const int p = pp[l], q = qq[l];
+          const double c = cc[l], s = ss[l];
+          const double vp = V[i * lda + p], vq = V[i * lda + q];
+          V[i * lda + p] = c * vp - s * vq;
+          V[i * lda + q] = s * vp + c * vq;
+        }
       }
       __syncthreads();
     }
@@ -162,10 +298,11 @@ __global__ __launch_bounds__(NT) void eigh_kernel(
   }
 }
 
+// rotation table (c, s, p, q per pair) + ranks + sorted eigenvalues
 static size_t eig_scratch_bytes(int n) {
-  const int half = (n + 1) / 2 + 1;
-  return (size_t)2 * half * sizeof(double) + (size_t)((n + 2) & ~1) * sizeof(int) +
-         (size_t)(n + 1) * sizeof(double);
+  const int half = (n + 1) / 2;
+  return (size_t)2 * half * sizeof(double) + (size_t)2 * half * sizeof(int) +
+         (size_t)2 * half * sizeof(int) + (size_t)(n + 1) * sizeof(double);
 }
 
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold, double* C,
@@ -173,21 +310,21 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* ws_eig, hipStream_t st) {
   if (!p.eig_small.empty()) {
     const int nmax = 32;
-    const size_t lds = 2 * (size_t)nmax * (nmax + 1) * sizeof(double) + eig_scratch_bytes(nmax);
-    hipLaunchKernelGGL((eigh_kernel<64, true>), dim3((unsigned)p.eig_small.size()), dim3(64), lds,
+    const size_t lds = 3 * (size_t)nmax * (nmax + 1) * sizeof(double) + eig_scratch_bytes(nmax);
+    hipLaunchKernelGGL((eigh_kernel<64, 32>), dim3((unsigned)p.eig_small.size()), dim3(64), lds,
                        st, p.d_frag, p.d_eig_small, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig,
                        nmax);
   }
   if (!p.eig_mid.empty()) {
     const int nmax = 48;
-    const size_t lds = 2 * (size_t)nmax * (nmax + 1) * sizeof(double) + eig_scratch_bytes(nmax);
-    hipLaunchKernelGGL((eigh_kernel<256, true>), dim3((unsigned)p.eig_mid.size()), dim3(256), lds,
+    const size_t lds = 3 * (size_t)nmax * (nmax + 1) * sizeof(double) + eig_scratch_bytes(nmax);
+    hipLaunchKernelGGL((eigh_kernel<256, 48>), dim3((unsigned)p.eig_mid.size()), dim3(256), lds,
                        st, p.d_frag, p.d_eig_mid, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig,
                        nmax);
   }
   if (!p.eig_large.empty()) {
     const int nmax = p.eig_large_max_nbf;
-    hipLaunchKernelGGL((eigh_kernel<1024, false>), dim3((unsigned)p.eig_large.size()), dim3(1024),
+    hipLaunchKernelGGL((eigh_kernel<1024, 0>), dim3((unsigned)p.eig_large.size()), dim3(1024),
                        eig_scratch_bytes(nmax), st, p.d_frag, p.d_eig_large, F, Dold, C, eps,
                        Dnew, dD_max, flags, ws_eig, nmax);
   }

@@ -50,36 +50,53 @@ __global__ __launch_bounds__(256) void moments_kernel(const FragInfo* __restrict
 }
 
 // phi^x.  The neighbour moments are first summed per class,
-// e_c = sum_{y in nbr(x), c(y) = c} s_xy d^y (fixed neighbour order), then
-// phi^x = sum_c G_{c(x) c} e_c with G_{c,0} stored and G_{0,c} = G_{c,0}^T.
+// e_c = sum_{y in nbr(x), c(y) = c} s_xy d^y, then phi^x = sum_c G_{c(x) c} e_c
+// with G_{c,0} stored and G_{0,c} = G_{c,0}^T.  Wave w takes the neighbours
+// w, w + 4, ... of x in list order and keeps class-0 sums in registers
+// (rows lane, lane + 64 of the P0 vector); the four wave partials are added
+// in wave order, so the result is deterministic.
 __global__ __launch_bounds__(256) void field_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ nbr_ptr,
     const int32_t* __restrict__ nbr_idx, const double* __restrict__ nbr_s,
     const double* __restrict__ G, const int64_t* __restrict__ off_G, int P0, int nclass,
     const int32_t* __restrict__ naux_cls_off, const double* __restrict__ dmom,
     double* __restrict__ phi) {
-  extern __shared__ double e[];  // concatenated e_c, sum of P_c over classes
+  extern __shared__ double part[];  // [4][etot] per-wave partial e_c, then e
   const int x = blockIdx.x;
-  const FragInfo fx = frag[x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int etot = naux_cls_off[nclass];
-  for (int t = threadIdx.x; t < etot; t += blockDim.x) e[t] = 0.0;
+  for (int t = threadIdx.x; t < 4 * etot; t += blockDim.x) part[t] = 0.0;
   __syncthreads();
+  double* mine = part + wave * etot;
   const int beg = nbr_ptr[x], end = nbr_ptr[x + 1];
-  for (int k = beg; k < end; ++k) {
+  double e0 = 0.0, e1 = 0.0;
+#pragma unroll 4
+  for (int k = beg + wave; k < end; k += 4) {
     const int y = nbr_idx[k];
     const double s = nbr_s[k];
-    const FragInfo fy = frag[y];
-    const int base = naux_cls_off[fy.cls];
-    const double* dy = dmom + fy.off_aux;
-    for (int q = threadIdx.x; q < fy.naux; q += blockDim.x) e[base + q] = fma(s, dy[q], e[base + q]);
+    const int cy = frag[y].cls;
+    const double* dy = dmom + frag[y].off_aux;
+    if (cy == 0) {
+      if (lane < P0) e0 = fma(s, dy[lane], e0);
+      if (lane + 64 < P0) e1 = fma(s, dy[lane + 64], e1);
+    } else {
+      const int base = naux_cls_off[cy], pc = frag[y].naux;
+      for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
+    }
   }
+  if (lane < P0) mine[lane] += e0;
+  if (lane + 64 < P0) mine[lane + 64] += e1;
   __syncthreads();
+  for (int q = threadIdx.x; q < etot; q += blockDim.x)
+    part[q] = ((part[q] + part[etot + q]) + part[2 * etot + q]) + part[3 * etot + q];
+  __syncthreads();
+  const FragInfo fx = frag[x];
   const int cx = fx.cls;
   for (int p = threadIdx.x; p < fx.naux; p += blockDim.x) {
     double acc = 0.0;
     for (int c = 0; c < nclass; ++c) {
       const int pc = naux_cls_off[c + 1] - naux_cls_off[c];
-      const double* ec = e + naux_cls_off[c];
+      const double* ec = part + naux_cls_off[c];
       if (c == 0) {
         const double* g = G + off_G[cx];  // G_{cx,0}: [P_cx][P0]
         for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)p * P0 + q], ec[q], acc);
@@ -129,7 +146,7 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G, c
   hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 3) / 4), dim3(256), 0, st,
                      p.d_frag, B, D, ws_d);
   const int etot = p.naux_cls_off.back();
-  hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), etot * sizeof(double), st, p.d_frag,
+  hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                      p.d_naux_cls_off, ws_d, ws_phi);
   const int nnmax = p.max_nbf * p.max_nbf;

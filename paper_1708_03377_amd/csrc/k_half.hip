@@ -7,10 +7,176 @@
 // The contraction is done occupied side first (X = C_occ^T B_P, then
 // X C_vir), the cheaper order for nocc < nvir.  Both steps read every element
 // of B once; the kernel is bound by HBM bandwidth.
+#include <algorithm>
+
 #include "fef_internal.h"
 #include "fef_device.h"
+#include "fef_split.h"
 
 namespace fef {
+
+// Half transform of small fragments (nbf <= 32, one 96-wide tile, P_c <= 80)
+// in two kernels.
+//  ht_mo_small_kernel: one workgroup per (fragment, 8 factor slices): the 8
+//    slices of B^x (8 nbf^2 doubles) are staged in LDS with 16-byte loads,
+//    then X = C_occ^T B_P and B_ov = X C_vir are formed from LDS and B_ov is
+//    written densely.  Thousands of workgroups keep HBM streaming.
+//  ht_pack_small_kernel: one workgroup per fragment: B_ov^x in LDS, W^x =
+//    G^T B_ov^x in registers (up to kMaxW outputs per thread), and both
+//    pair-kernel operands of mode PREC written directly (FP16 scales from
+//    block-wide maxima).
+constexpr int kSmallP = 80, kSliceGroup = 8;
+constexpr int kMaxW = (kSmallP * kTile + 255) / 256;
+
+__global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __restrict__ frag,
+                                                          const int32_t* __restrict__ list,
+                                                          const double* __restrict__ B,
+                                                          const double* __restrict__ C,
+                                                          double* __restrict__ bov, int max_nn) {
+  extern __shared__ double sm[];
+  double* Cs = sm;                                  // [nbf][nbf]
+  double* Bst = sm + max_nn;                        // [8][nbf][nbf]
+  double* Xs = sm + (1 + kSliceGroup) * max_nn;     // [8][nocc][nbf]
+  const FragInfo fi = frag[list[blockIdx.x]];
+  const int p0 = blockIdx.y * kSliceGroup;
+  if (p0 >= fi.naux) return;
+  const int np = min(kSliceGroup, fi.naux - p0);
+  const int n = fi.nbf, o = fi.nocc, v = fi.nvir, ov = fi.ov, nn = n * n;
+  for (int e = threadIdx.x; e < nn; e += 256) Cs[e] = C[fi.off_C + e];
+  const double* src = B + fi.off_B + (int64_t)p0 * nn;
+  const int tot = np * nn;  // nn is even unless n is odd; stage in pairs when aligned
+  if ((nn & 1) == 0 && ((fi.off_B + (int64_t)p0 * nn) & 1) == 0) {
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+    double2* d2 = reinterpret_cast<double2*>(Bst);
+    for (int e = threadIdx.x; e < tot / 2; e += 256) d2[e] = s2[e];
+  } else {
+    for (int e = threadIdx.x; e < tot; e += 256) Bst[e] = src[e];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < np * o * n; e += 256) {  // X = C_occ^T B_P
+    const int pp = e / (o * n), r = e - pp * (o * n);
+    const int i = r / n, nu = r - (r / n) * n;
+    const double* b = Bst + pp * nn + nu;
+    double acc = 0.0;
+    for (int mu = 0; mu < n; ++mu) acc = fma(Cs[mu * n + i], b[mu * n], acc);
+    Xs[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < np * ov; e += 256) {  // B_ov = X C_vir
+    const int pp = e / ov, r = e - pp * ov;
+    const int i = r / v, a = r - (r / v) * v;
+    const double* xr = Xs + (pp * o + i) * n;
+    double acc = 0.0;
+    for (int nu = 0; nu < n; ++nu) acc = fma(xr[nu], Cs[nu * n + o + a], acc);
+    bov[fi.off_bov + (int64_t)(p0 + pp) * ov + r] = acc;
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void ht_pack_small_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
+    const double* __restrict__ bov, const double* __restrict__ G,
+    const int64_t* __restrict__ off_G, int P0, int kpad, int pw, double* __restrict__ w_out,
+    char* __restrict__ ops) {
+  __shared__ double Bs[kSmallP * kTile];
+  __shared__ double red[4];
+  const int f = list[blockIdx.x];
+  const FragInfo fi = frag[f];
+  const int ov = fi.ov, P = fi.naux;
+  for (int e = threadIdx.x; e < P * ov; e += 256) Bs[e] = bov[fi.off_bov + e];
+  __syncthreads();
+  // W = G_{c,0}^T B_ov into registers
+  const double* g = G + off_G[fi.cls];  // [P][P0]
+  double wv[kMaxW];
+  double wmax = 0.0, bmax = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxW; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    double acc = 0.0;
+    if (e < P0 * ov) {
+      const int q = e / ov, ia = e - (e / ov) * ov;
+      for (int pp = 0; pp < P; ++pp) acc = fma(g[(int64_t)pp * P0 + q], Bs[pp * ov + ia], acc);
+    }
+    wv[u] = acc;
+    wmax = fmax(wmax, fabs(acc));
+  }
+  for (int e = threadIdx.x; e < P * ov; e += 256) bmax = fmax(bmax, fabs(Bs[e]));
+  if (w_out) {
+#pragma unroll
+    for (int u = 0; u < kMaxW; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < P0 * ov) w_out[fi.off_w + e] = wv[u];
+    }
+  }
+  const bool right = fi.off_R[PREC] >= 0;
+  if (PREC == FEF_F64 || PREC == FEF_F32) {
+    typedef typename std::conditional<PREC == FEF_F64, double, float>::type T;
+    T* L = reinterpret_cast<T*>(ops + fi.off_L[PREC]);
+    T* R = right ? reinterpret_cast<T*>(ops + fi.off_R[PREC]) : nullptr;
+    // [kpad][ld]: values, then zeros in the padding
+#pragma unroll
+    for (int u = 0; u < kMaxW; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < P0 * ov) {
+        const int q = e / ov, ia = e - (e / ov) * ov;
+        L[(int64_t)q * fi.ld + ia] = (T)wv[u];
+      }
+    }
+    for (int e = threadIdx.x; e < kpad * kTile; e += 256) {
+      const int k = e / kTile, m = e - (e / kTile) * kTile;
+      if (k >= P0 || m >= ov) {
+        L[(int64_t)k * fi.ld + m] = (T)0;
+        if (R) R[(int64_t)k * fi.ld + m] = (T)0;
+      } else if (R) {
+        R[(int64_t)k * fi.ld + m] = (T)Bs[k * ov + m];
+      }
+    }
+  } else {
+    constexpr bool kF16 = PREC == FEF_FP16X2;
+    wmax = block_max(wmax, red);
+    bmax = block_max(bmax, red);
+    const double sL = kF16 ? split_scale(wmax) : 1.0;
+    const double sR = kF16 ? split_scale(bmax) : 1.0;
+    double* hdr = reinterpret_cast<double*>(ops);
+    if (threadIdx.x == 0) {
+      hdr[2 * f] = 1.0 / sL;
+      hdr[2 * f + 1] = 1.0 / sR;
+    }
+    const int xs = 2 * pw + 8;
+    uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
+    uint16_t* R = right ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
+#pragma unroll
+    for (int u = 0; u < kMaxW; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < P0 * ov) {
+        const int q = e / ov, ia = e - (e / ov) * ov;
+        uint16_t hi, lo;
+        split2<kF16>(wv[u] * sL, hi, lo);
+        L[ia * xs + q] = hi;
+        L[ia * xs + pw + q] = lo;
+      }
+    }
+    if (R)
+      for (int e = threadIdx.x; e < P0 * ov; e += 256) {
+        const int q = e / ov, ia = e - (e / ov) * ov;
+        uint16_t hi, lo;
+        split2<kF16>(Bs[q * ov + ia] * sR, hi, lo);
+        R[ia * xs + q] = hi;
+        R[ia * xs + pw + q] = lo;
+      }
+    // zeros: rows past ov, and the columns past P0 in each plane plus the tail
+    const int pad = pw - P0;
+    for (int e = threadIdx.x; e < kTile * xs; e += 256) {
+      const int m = e / xs, k = e - (e / xs) * xs;
+      const bool z = m >= ov || (k >= P0 && k < pw) || k >= pw + P0;
+      if (z) {
+        L[e] = 0;
+        if (R) R[e] = 0;
+      }
+    }
+    (void)pad;
+  }
+}
 
 // One task = one fragment and up to 8 consecutive factor indices P.
 __global__ __launch_bounds__(256) void ht_bov_kernel(const FragInfo* __restrict__ frag,
@@ -46,11 +212,12 @@ __global__ __launch_bounds__(256) void ht_bov_kernel(const FragInfo* __restrict_
 
 // W^x[Q][ia] for Q in [8*blockIdx.y, +8).
 __global__ __launch_bounds__(256) void ht_w_kernel(const FragInfo* __restrict__ frag,
+                                                   const int32_t* __restrict__ list,
                                                    const double* __restrict__ G,
                                                    const int64_t* __restrict__ off_G, int P0,
                                                    const double* __restrict__ bov,
                                                    double* __restrict__ w) {
-  const FragInfo fi = frag[blockIdx.x];
+  const FragInfo fi = frag[list[blockIdx.x]];
   if (fi.ov == 0) return;
   const double* g = G + off_G[fi.cls];  // [P_c][P0]
   const double* b = bov + fi.off_bov;   // [P_c][ov]
@@ -68,11 +235,12 @@ __global__ __launch_bounds__(256) void ht_w_kernel(const FragInfo* __restrict__ 
 // [kpad][ld] (row k, column ia), zero padded in both directions.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_plain_kernel(const FragInfo* __restrict__ frag,
+                                                         const int32_t* __restrict__ list,
                                                          int P0, int kpad, int prec,
                                                          const double* __restrict__ bov,
                                                          const double* __restrict__ w,
                                                          char* __restrict__ ops) {
-  const FragInfo fi = frag[blockIdx.x];
+  const FragInfo fi = frag[list[blockIdx.x]];
   const int k = blockIdx.y;
   if (fi.ld == 0) return;
   T* L = reinterpret_cast<T*>(ops + fi.off_L[prec]) + (int64_t)k * fi.ld;
@@ -87,29 +255,54 @@ __global__ __launch_bounds__(256) void pack_plain_kernel(const FragInfo* __restr
 
 hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const double* C,
                                  const double* G, double* bov, double* w, void* ops,
-                                 fef_prec prec, hipStream_t st) {
-  if (p.ht_ntasks > 0) {
-    const size_t lds = (size_t)std::max<int64_t>(p.max_on, 1) * sizeof(double);
-    hipLaunchKernelGGL(ht_bov_kernel, dim3((unsigned)p.ht_ntasks), dim3(256), lds, st,
-                       p.d_frag, p.d_ht, B, C, bov);
-    hipLaunchKernelGGL(ht_w_kernel, dim3(p.nfrag, (p.P0 + 7) / 8), dim3(256), 0, st, p.d_frag,
-                       G, p.d_off_G, p.P0, bov, w);
-  }
-  const int kpad = p.geom[prec].kpad;
+                                 fef_prec prec, hipStream_t st, bool dense_out) {
   char* o = static_cast<char*>(ops);
-  switch (prec) {
-    case FEF_F64:
-      hipLaunchKernelGGL(pack_plain_kernel<double>, dim3(p.nfrag, kpad), dim3(256), 0, st,
-                         p.d_frag, p.P0, kpad, (int)prec, bov, w, o);
-      break;
-    case FEF_F32:
-      hipLaunchKernelGGL(pack_plain_kernel<float>, dim3(p.nfrag, kpad), dim3(256), 0, st,
-                         p.d_frag, p.P0, kpad, (int)prec, bov, w, o);
-      break;
-    default:
-      return launch_pack_split(p, bov, w, ops, prec, st);
+  const int kpad = p.geom[prec].kpad, pw = p.geom[prec].pw;
+  if (!p.ht_fused.empty()) {
+    double* wo = dense_out ? w : nullptr;
+    const dim3 grid((unsigned)p.ht_fused.size());
+    const size_t lds = (size_t)((1 + kSliceGroup) * p.fuse_lds[0] + kSliceGroup * p.fuse_lds[1]) *
+                       sizeof(double);
+    hipLaunchKernelGGL(ht_mo_small_kernel,
+                       dim3(grid.x, (p.max_naux_small + kSliceGroup - 1) / kSliceGroup),
+                       dim3(256), lds, st, p.d_frag, p.d_ht_fused, B, C, bov, p.fuse_lds[0]);
+#define FEF_FUSED(M)                                                                              \
+  hipLaunchKernelGGL(ht_pack_small_kernel<M>, grid, dim3(256), 0, st, p.d_frag, p.d_ht_fused,     \
+                     bov, G, p.d_off_G, p.P0, kpad, pw, wo, o)
+    switch (prec) {
+      case FEF_F64: FEF_FUSED(FEF_F64); break;
+      case FEF_F32: FEF_FUSED(FEF_F32); break;
+      case FEF_BF16X2: FEF_FUSED(FEF_BF16X2); break;
+      default: FEF_FUSED(FEF_FP16X2); break;
+    }
+#undef FEF_FUSED
+  }
+  if (!p.ht_generic.empty()) {
+    const unsigned ng = (unsigned)p.ht_generic.size();
+    if (p.ht_ntasks > 0) {
+      const size_t lds = (size_t)std::max<int64_t>(p.max_on, 1) * sizeof(double);
+      hipLaunchKernelGGL(ht_bov_kernel, dim3((unsigned)p.ht_ntasks), dim3(256), lds, st,
+                         p.d_frag, p.d_ht, B, C, bov);
+      hipLaunchKernelGGL(ht_w_kernel, dim3(ng, (p.P0 + 7) / 8), dim3(256), 0, st, p.d_frag,
+                         p.d_ht_generic, G, p.d_off_G, p.P0, bov, w);
+    }
+    switch (prec) {
+      case FEF_F64:
+        hipLaunchKernelGGL(pack_plain_kernel<double>, dim3(ng, kpad), dim3(256), 0, st, p.d_frag,
+                           p.d_ht_generic, p.P0, kpad, (int)prec, bov, w, o);
+        break;
+      case FEF_F32:
+        hipLaunchKernelGGL(pack_plain_kernel<float>, dim3(ng, kpad), dim3(256), 0, st, p.d_frag,
+                           p.d_ht_generic, p.P0, kpad, (int)prec, bov, w, o);
+        break;
+      default: {
+        hipError_t e = launch_pack_split(p, bov, w, ops, prec, st);
+        if (e != hipSuccess) return e;
+      }
+    }
   }
   return hipGetLastError();
 }
+
 
 }  // namespace fef

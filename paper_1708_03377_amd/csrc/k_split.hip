@@ -5,55 +5,36 @@
 // (rn = round to nearest even in the 16-bit format).  The product keeps the
 // three leading terms
 //     x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y
-// and drops lo_x lo_y.  The three products are laid out as ONE contraction
-// over a concatenated K axis of length 3 P0 (padded to a multiple of 32):
-//     left  row ia: [ hi(W^x) | hi(W^x) | lo(W^x) ]
-//     right row jb: [ hi(B^y) | lo(B^y) | hi(B^y) ]
-// so a single 16x16x32 MFMA chain computes all three.  FP16 operands carry a
+// and drops lo_x lo_y.  Each fragment stores one row per ia: [hi | lo], each
+// plane pw = round_up(P0, 8) wide.  The three products run as ONE contraction
+// over a concatenated axis of length 3 pw (padded to a multiple of 32):
+//     x (left)  segments: hi(W^x), hi(W^x), lo(W^x)
+//     y (right) segments: hi(B^y), lo(B^y), hi(B^y)
+// so a single 16x16x32 MFMA chain computes all three; pw is a multiple of 8,
+// so the 8 contraction indices a lane feeds one MFMA never straddle two
+// segments.  FP16 operands carry a
 // per-fragment power-of-two scale that places each operand's largest value
 // in [2^13, 2^14), keeping lo parts out of the subnormal range; the scales
 // are undone exactly in FP64.
+#include <algorithm>
+
 #include "fef_internal.h"
 #include "fef_device.h"
 #include "fef_epilogue.h"
+#include "fef_split.h"
 
 namespace fef {
-
-__device__ inline uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ inline double bf16_to_double(uint16_t h) {
-  return (double)__uint_as_float(((uint32_t)h) << 16);
-}
-__device__ inline uint16_t f16_rne(float f) {
-  _Float16 h = (_Float16)f;
-  return __builtin_bit_cast(uint16_t, h);
-}
-__device__ inline double f16_to_double(uint16_t h) {
-  return (double)__builtin_bit_cast(_Float16, h);
-}
-
-template <bool kFp16>
-__device__ inline void split2(double x, uint16_t& hi, uint16_t& lo) {
-  if (kFp16) {
-    hi = f16_rne((float)x);
-    lo = f16_rne((float)(x - f16_to_double(hi)));
-  } else {
-    hi = bf16_rne((float)x);
-    lo = bf16_rne((float)(x - bf16_to_double(hi)));
-  }
-}
 
 // Per-fragment scales: hdr[2 f] = 1 / scale_left, hdr[2 f + 1] = 1 / scale_right.
 template <bool kFp16>
 __global__ __launch_bounds__(256) void split_scale_kernel(const FragInfo* __restrict__ frag,
+                                                          const int32_t* __restrict__ list,
                                                           int P0, const double* __restrict__ bov,
                                                           const double* __restrict__ w,
                                                           double* __restrict__ hdr) {
   __shared__ double red[4];
-  const FragInfo fi = frag[blockIdx.x];
+  const int f = list[blockIdx.x];
+  const FragInfo fi = frag[f];
   double mL = 0.0, mR = 0.0;
   const int64_t nL = (int64_t)P0 * fi.ov;
   for (int64_t e = threadIdx.x; e < nL; e += blockDim.x) {
@@ -63,57 +44,59 @@ __global__ __launch_bounds__(256) void split_scale_kernel(const FragInfo* __rest
   mL = block_max(mL, red);
   mR = block_max(mR, red);
   if (threadIdx.x == 0) {
-    double sL = 1.0, sR = 1.0;
-    if (kFp16) {
-      int ex;
-      if (mL > 0.0) { frexp(mL, &ex); sL = ldexp(1.0, 14 - ex); }
-      if (mR > 0.0) { frexp(mR, &ex); sR = ldexp(1.0, 14 - ex); }
-    }
-    hdr[2 * blockIdx.x] = 1.0 / sL;
-    hdr[2 * blockIdx.x + 1] = 1.0 / sR;
+    const double sL = kFp16 ? split_scale(mL) : 1.0;
+    const double sR = kFp16 ? split_scale(mR) : 1.0;
+    hdr[2 * f] = 1.0 / sL;
+    hdr[2 * f + 1] = 1.0 / sR;
   }
 }
 
-// Writes the concatenated hi/lo operands, layout [ld][kc] (k contiguous).
+// Writes both operands of a fragment, layout [ld][2 pw + 8]: row m holds
+// hi(k = 0..P0-1), zeros up to pw, then lo(k), zeros, then 8 zeros; rows
+// m >= ov are zero.
 template <bool kFp16>
 __global__ __launch_bounds__(256) void split_pack_kernel(const FragInfo* __restrict__ frag,
-                                                         int P0, int kc, int prec,
+                                                         const int32_t* __restrict__ list,
+                                                         int P0, int pw, int prec,
                                                          const double* __restrict__ bov,
                                                          const double* __restrict__ w,
                                                          const double* __restrict__ hdr,
                                                          char* __restrict__ ops) {
-  const FragInfo fi = frag[blockIdx.x];
+  const int f = list[blockIdx.x];
+  const FragInfo fi = frag[f];
   const int tile = blockIdx.y;
   if (tile >= fi.ntile) return;
-  const double sL = 1.0 / hdr[2 * blockIdx.x];
-  const double sR = 1.0 / hdr[2 * blockIdx.x + 1];
+  const double sL = 1.0 / hdr[2 * f];
+  const double sR = 1.0 / hdr[2 * f + 1];
   uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[prec]);
   uint16_t* R = fi.off_R[prec] >= 0 ? reinterpret_cast<uint16_t*>(ops + fi.off_R[prec]) : nullptr;
-  const int nchunk = kc / 8;
+  const int nchunk = pw / 8;
+  const int row2 = 2 * pw + 8;
+  const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int m = tile * kTile + threadIdx.x; m < (tile + 1) * kTile; m += blockDim.x) {
+    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + 2 * pw) = z;
+    if (R) *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + 2 * pw) = z;
+  }
   for (int e = threadIdx.x; e < kTile * nchunk; e += blockDim.x) {
     const int m = tile * kTile + e / nchunk;
     const int k0 = (e % nchunk) * 8;
-    u16x8 vl, vr;
+    u16x8 lh, ll, rh, rl;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int kk = k0 + u;
-      const int seg = kk / P0;
-      const int k = kk - seg * P0;
-      uint16_t l = 0, r = 0;
-      if (m < fi.ov && seg < 3) {
-        uint16_t hi, lo;
-        split2<kFp16>(w[fi.off_w + (int64_t)k * fi.ov + m] * sL, hi, lo);
-        l = (seg == 2) ? lo : hi;
-        if (R) {
-          split2<kFp16>(bov[fi.off_bov + (int64_t)k * fi.ov + m] * sR, hi, lo);
-          r = (seg == 1) ? lo : hi;
-        }
+      const int k = k0 + u;
+      uint16_t a = 0, b = 0, c = 0, d = 0;
+      if (m < fi.ov && k < P0) {
+        split2<kFp16>(w[fi.off_w + (int64_t)k * fi.ov + m] * sL, a, b);
+        if (R) split2<kFp16>(bov[fi.off_bov + (int64_t)k * fi.ov + m] * sR, c, d);
       }
-      vl[u] = l;
-      vr[u] = r;
+      lh[u] = a; ll[u] = b; rh[u] = c; rl[u] = d;
     }
-    *reinterpret_cast<u16x8*>(L + (int64_t)m * kc + k0) = vl;
-    if (R) *reinterpret_cast<u16x8*>(R + (int64_t)m * kc + k0) = vr;
+    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + k0) = lh;
+    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + pw + k0) = ll;
+    if (R) {
+      *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + k0) = rh;
+      *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + pw + k0) = rl;
+    }
   }
 }
 
@@ -121,20 +104,21 @@ hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const doubl
                              fef_prec prec, hipStream_t st) {
   char* o = static_cast<char*>(ops);
   double* hdr = reinterpret_cast<double*>(o);
-  const int kc = p.geom[prec].kpad;
+  const int pw = p.geom[prec].pw;
   int maxtile = 0;
-  for (const auto& f : p.frag) maxtile = f.ntile > maxtile ? f.ntile : maxtile;
+  for (int32_t f : p.ht_generic) maxtile = std::max(maxtile, p.frag[f].ntile);
   if (maxtile == 0) return hipSuccess;
+  const unsigned ng = (unsigned)p.ht_generic.size();
   if (prec == FEF_FP16X2) {
-    hipLaunchKernelGGL(split_scale_kernel<true>, dim3(p.nfrag), dim3(256), 0, st, p.d_frag, p.P0,
-                       bov, w, hdr);
-    hipLaunchKernelGGL(split_pack_kernel<true>, dim3(p.nfrag, maxtile), dim3(256), 0, st,
-                       p.d_frag, p.P0, kc, (int)prec, bov, w, hdr, o);
+    hipLaunchKernelGGL(split_scale_kernel<true>, dim3(ng), dim3(256), 0, st, p.d_frag,
+                       p.d_ht_generic, p.P0, bov, w, hdr);
+    hipLaunchKernelGGL(split_pack_kernel<true>, dim3(ng, maxtile), dim3(256), 0, st, p.d_frag,
+                       p.d_ht_generic, p.P0, pw, (int)prec, bov, w, hdr, o);
   } else if (prec == FEF_BF16X2) {
-    hipLaunchKernelGGL(split_scale_kernel<false>, dim3(p.nfrag), dim3(256), 0, st, p.d_frag,
-                       p.P0, bov, w, hdr);
-    hipLaunchKernelGGL(split_pack_kernel<false>, dim3(p.nfrag, maxtile), dim3(256), 0, st,
-                       p.d_frag, p.P0, kc, (int)prec, bov, w, hdr, o);
+    hipLaunchKernelGGL(split_scale_kernel<false>, dim3(ng), dim3(256), 0, st, p.d_frag,
+                       p.d_ht_generic, p.P0, bov, w, hdr);
+    hipLaunchKernelGGL(split_pack_kernel<false>, dim3(ng, maxtile), dim3(256), 0, st, p.d_frag,
+                       p.d_ht_generic, p.P0, pw, (int)prec, bov, w, hdr, o);
   } else {
     return hipErrorInvalidValue;
   }
@@ -151,64 +135,192 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// Same decomposition as the plain kernel: 4 waves x (3x3) 16x16 tiles of V.
-// A-operand lane layout of the 16x16x32 MFMA: row = lane % 16, k = 8 (lane /
-// 16) .. +7; the B operand mirrors it with column = lane % 16.
-template <bool kFp16>
-__global__ __launch_bounds__(256) void pair_split_kernel(
+// Persistent split-precision pair kernel (8 waves).  Work items as in the
+// plain kernel.  A workgroup serves XB x units (XB = 4: two waves per unit,
+// 48x96 each; XB = 2: four waves per unit, 48x48 each).  Every wave keeps
+// its x rows' MFMA A fragments (rows [hi|lo] of W^x, all NCH contraction
+// chunks) in registers for the whole item; the streamed y tiles (rows
+// [hi|lo] of B^y, with their gaps) pass through a double-buffered LDS stage
+// shared by all units, the next tile being fetched into registers while the
+// current one is contracted.  Two waves per SIMD let one wave's FP32
+// epilogue run beside the other's MFMA chain.  MFMA operand lane layout
+// (16x16x32): row (or column) = lane % 16, contraction indices 8 (lane / 16)
+// .. +7.
+template <bool kFp16, int XB, int NCH>
+__global__ __launch_bounds__(512) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
-    const Item* __restrict__ items, const char* __restrict__ ops, int prec, int kc,
-    const double* __restrict__ eps, double* __restrict__ partial, int32_t* __restrict__ flags) {
-  __shared__ double red[4];
-  const Item it = items[blockIdx.x];
-  const PairInfo pr = pairs[it.pair];
-  const FragInfo fx = frag[pr.x];
-  const FragInfo fy = frag[pr.y];
-  const double* hdr = reinterpret_cast<const double*>(ops);
-  const double scale = hdr[2 * pr.x] * hdr[2 * pr.y + 1];
-  const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + fx.off_L[prec]);
-  const uint16_t* R = reinterpret_cast<const uint16_t*>(ops + fy.off_R[prec]);
+    const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
+    const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
+    int32_t* __restrict__ head, const char* __restrict__ ops, int prec, int pw,
+    const double* __restrict__ gap, double* __restrict__ partial) {
+  constexpr int NT = 512, NW = 8;
+  constexpr int WPU = NW / XB;
+  constexpr int TI = 3;
+  constexpr int TJ = XB == 4 ? 6 : 3;
+  constexpr int NPF = (kTile * (2 * 80 + 8) / 8 + NT - 1) / NT;  // staging chunks per thread
+  extern __shared__ char smem[];
+  const int xs = 2 * pw + 8;  // row stride (16-bit elements) in HBM and LDS
+  uint16_t* Ys = reinterpret_cast<uint16_t*>(smem);  // [2][kTile][xs]
+  __shared__ float Gx[XB * kTile];
+  __shared__ float Gy[2][kTile];
+  __shared__ double red[2][NW];
+  __shared__ int32_t s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = it.mt * kTile + (wave >> 1) * 48;
-  const int c0 = it.nt * kTile + (wave & 1) * 48;
-  f4 acc[3][3];
+  const int unit = wave / WPU, sub = wave % WPU;
+  const int r0 = XB == 4 ? sub * 48 : (sub >> 1) * 48;
+  const int c0 = XB == 4 ? 0 : (sub & 1) * 48;
+  const double* hdr = reinterpret_cast<const double*>(ops);
+  const int tile_ch = kTile * xs / 8;  // 16-byte chunks per tile
+  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  // this lane's contraction segments: x reads hi, hi, lo; y reads hi, lo,
+  // hi; indices past 3 pw read the 8 zeros that end every stored row
+  int xoff[NCH], yoff[NCH];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) acc[i][j] = f4{0, 0, 0, 0};
-  for (int k = 0; k < kc; k += 32) {
-    u16x8 a[3], b[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      a[i] = *reinterpret_cast<const u16x8*>(L + (int64_t)(r0 + 16 * i + li) * kc + k + 8 * lk);
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      b[j] = *reinterpret_cast<const u16x8*>(R + (int64_t)(c0 + 16 * j + li) * kc + k + 8 * lk);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) acc[i][j] = mma16<kFp16>(a[i], b[j], acc[i][j]);
+  for (int c = 0; c < NCH; ++c) {
+    const int kk = 32 * c + 8 * lk;
+    const int seg = kk / pw;
+    const int off = kk - seg * pw;
+    xoff[c] = seg < 3 ? (seg == 2 ? pw : 0) + off : 2 * pw;
+    yoff[c] = seg < 3 ? (seg == 1 ? pw : 0) + off : 2 * pw;
   }
-  const double sum = weighted_tiles<false>(acc, r0, c0, lane, fx, fy, eps + fx.off_eps,
-                                       eps + fy.off_eps, flags, scale);
-  const double total = block_sum(sum, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = 4.0 * pr.s * pr.s * total;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+    __syncthreads();
+    const int32_t it = s_item;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
+    const int fxi = xblocks[xbid].f[unit];
+    const int mt = xblocks[xbid].mt[unit];
+    const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
+    u16x8 xa[TI][NCH];
+    if (fxi >= 0) {
+      const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
+                          (int64_t)(mt * kTile + r0 + li) * xs;
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+          xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) xa[i][c] = zero;
+    }
+    for (int t = threadIdx.x; t < XB * kTile; t += NT) {
+      const int u = t / kTile, m = t - (t / kTile) * kTile;
+      const int f = xblocks[xbid].f[u];
+      Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
+    }
+    u16x8 pf[NPF];
+    float pg = 0.0f;
+#define FEF_ISSUE(E)                                                                            \
+  {                                                                                             \
+    const int y_ = entries[E].y, nt_ = entries[E].nt;                                           \
+    const u16x8* R_ = reinterpret_cast<const u16x8*>(ops + frag[y_].off_R[prec]) +              \
+                      (int64_t)nt_ * tile_ch;                                                   \
+    _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
+      const int c_ = threadIdx.x + NT * k_;                                                     \
+      if (c_ < tile_ch) pf[k_] = R_[c_];                                                        \
+    }                                                                                           \
+    if (threadIdx.x < kTile) pg = (float)gap[frag[y_].off_gap + nt_ * kTile + threadIdx.x];     \
+  }
+#define FEF_STORE(B)                                                                            \
+  {                                                                                             \
+    u16x8* d_ = reinterpret_cast<u16x8*>(Ys + (B) * kTile * xs);                                \
+    _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
+      const int c_ = threadIdx.x + NT * k_;                                                     \
+      if (c_ < tile_ch) d_[c_] = pf[k_];                                                        \
+    }                                                                                           \
+    if (threadIdx.x < kTile) Gy[B][threadIdx.x] = pg;                                           \
+  }
+    FEF_ISSUE(e0)
+    FEF_STORE(0)
+    __syncthreads();
+    const int end = e0 + ne;
+    for (int e = e0; e < end; ++e) {
+      const int cur = (e - e0) & 1;
+      if (e + 1 < end) FEF_ISSUE(e + 1)
+      const int slot = entries[e].slot[unit];
+      double mine = 0.0;
+      if (slot >= 0) {
+        const uint16_t* Yb = Ys + cur * kTile * xs + (c0 + li) * xs;
+        f4 acc[TI][TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          u16x8 b[TJ];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoff[c]);
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+        }
+        mine = wave_sum(weighted_tiles_f32<TI, TJ>(acc, Gx + unit * kTile + r0, Gy[cur] + c0, lane));
+      }
+      if (lane == 0) red[cur][wave] = mine;
+      if (e + 1 < end) FEF_STORE(cur ^ 1)
+      __syncthreads();
+      if (sub == 0 && lane == 0 && slot >= 0) {
+        double t = 0.0;
+        for (int q = 0; q < WPU; ++q) t += red[cur][unit * WPU + q];
+        const double s = pairs[slot_pair[slot]].s;
+        const double sc = sx * hdr[2 * entries[e].y + 1];
+        partial[slot] = 4.0 * s * s * sc * sc * t;
+      }
+    }
+#undef FEF_ISSUE
+#undef FEF_STORE
+  }
 }
 
-hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* eps,
-                              fef_prec prec, double* partial, int32_t* flags, hipStream_t st) {
+size_t split_lds_bytes(int pw) { return (size_t)2 * kTile * (2 * pw + 8) * 2; }
+
+template <bool F16, int XB>
+static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds, hipStream_t st,
+                             const char* o, int prec, int pw, const double* gap, double* partial,
+                             int32_t* head) {
+  const TileSet& t = p.tiles[prec];
+  switch (nch) {
+#define FEF_NCH(N)                                                                                \
+  case N:                                                                                         \
+    hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(512), lds, st, p.d_frag,       \
+                       p.d_pair, p.d_slot_pair, t.d_xblocks, t.d_entries, t.d_items,              \
+                       (int32_t)t.nitems, head, o, prec, pw, gap, partial);                       \
+    break;
+    FEF_NCH(1) FEF_NCH(2) FEF_NCH(3) FEF_NCH(4) FEF_NCH(5) FEF_NCH(6) FEF_NCH(7) FEF_NCH(8)
+#undef FEF_NCH
+  }
+}
+
+hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
+                              fef_prec prec, double* partial, int32_t* head, int grid,
+                              hipStream_t st) {
   const char* o = static_cast<const char*>(ops);
-  const int kc = p.geom[prec].kpad;
-  if (prec == FEF_FP16X2)
-    hipLaunchKernelGGL(pair_split_kernel<true>, dim3((unsigned)p.nitems), dim3(256), 0, st,
-                       p.d_frag, p.d_pair, p.d_item, o, (int)prec, kc, eps, partial, flags);
-  else if (prec == FEF_BF16X2)
-    hipLaunchKernelGGL(pair_split_kernel<false>, dim3((unsigned)p.nitems), dim3(256), 0, st,
-                       p.d_frag, p.d_pair, p.d_item, o, (int)prec, kc, eps, partial, flags);
-  else
+  const int pw = p.geom[prec].pw, nch = p.geom[prec].kpad / 32;
+  const int xb = p.tiles[prec].xb;
+  if (pw > 80 || nch < 1 || nch > 8) return hipErrorInvalidValue;
+  const size_t lds = split_lds_bytes(pw);
+  const dim3 g(grid);
+  if (prec == FEF_FP16X2) {
+    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+    else launch_split_nch<true, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+  } else if (prec == FEF_BF16X2) {
+    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+    else launch_split_nch<false, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+  } else {
     return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
+
+void configure_split_kernels(int pw) { (void)pw; }
 
 }  // namespace fef

@@ -184,3 +184,24 @@ def test_reduced_precision_config0(torch, prec, tol_pair):
     err = np.max(np.abs(E2 - ref))
     _say(prec, "max pair err", err, "total err", tot - ref_tot)
     assert err <= tol_pair
+
+
+@pytest.mark.parametrize("prec,tiles", [("f64", [(1, 1), (1, 7)]), ("f32", [(1, 3)]),
+                                        ("bf16x2", [(2, 2), (2, 5), (4, 64)]),
+                                        ("fp16x2", [(2, 1), (4, 3)])])
+def test_tilings_agree(torch, prec, tiles):
+    """Every pair-kernel tiling gives the same pair energies (up to in-tile
+    summation order), on ragged and two-class systems."""
+    import paper_1708_03377_amd as lib
+    for sysm in (ragged_system(), two_class_system()):
+        ref, _ = ofef.pair_energies(sysm)
+        ctx = ctx_for(sysm)
+        base = ctx.energies(PREC[prec])[0].cpu().numpy().copy()
+        tol = TOL_PAIR_F64 if prec == "f64" else 1e-5
+        assert np.max(np.abs(base - ref)) <= tol
+        for xb, yc in tiles:
+            _say(prec, "tiles", xb, yc)
+            lib.fef_plan_set_tiles(ctx.plan, PREC[prec], xb, yc)
+            assert lib.fef_plan_get_tiles(ctx.plan, PREC[prec]) == (xb, yc)
+            got = ctx.pair_energies(PREC[prec])[0].cpu().numpy()
+            np.testing.assert_allclose(got, base, rtol=1e-12 if prec == "f64" else 1e-6, atol=0)
