@@ -184,6 +184,53 @@ fef_status fef_scf_step(fef_plan plan, const double* B, const double* G,
                         double* eps, double* D, double* dD_max, int32_t* flags,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Captured FEF pass.  All pointers are device pointers that stay valid for
+ * the graph's lifetime; the graph bakes them in. */
+typedef struct {
+  const double* B;
+  const double* G;
+  const double* F0;
+  const double* htilde;   /* nullable */
+  const double* C0;       /* nullable: copied into C (and eps0 into eps)
+                             before the SCF steps */
+  const double* eps0;     /* nullable together with C0 */
+  double* C;
+  double* eps;
+  double* D;              /* nullable */
+  double* dD_max;
+  int32_t* flags;
+  void* ops;              /* operand pool of mode `prec` */
+  double* E2_pair;
+  double* E2_total;
+  void* ws;               /* workspace, FEF_Q_SCF_WS_BYTES, FEF_Q_HALF_WS_BYTES
+                             and FEF_Q_PAIR_WS_BYTES bytes are all needed */
+  size_t ws_bytes;
+} fef_pass_args;
+
+typedef struct fef_graph_s* fef_graph;
+
+/* Records one whole FEF pass -- [reset of C, eps], niter SCF steps
+ * (fef_scf_step), the half transform and the pair energies in mode `prec`
+ * -- into a HIP graph (stream capture on a private default-priority stream;
+ * no allocation happens during replay).  Call outside any capture; the plan
+ * and every buffer must outlive the graph.  Replays run the same kernels in
+ * the same order as the eager calls, so results are bitwise identical to
+ * them. */
+fef_status fef_graph_create(fef_plan plan, const fef_pass_args* args, int32_t niter,
+                            fef_prec prec, fef_graph* out);
+fef_status fef_graph_launch(fef_graph graph, void* stream);
+fef_status fef_graph_destroy(fef_graph graph);
+
+/* Tile autotuner for mode `prec`: times every supported tiling of the pair
+ * kernel on this plan's own work (the operand pool must hold the half
+ * transform of mode `prec`), with `reps` timed launches each after one
+ * warm-up, keeps the fastest (fef_plan_set_tiles) and returns its x units
+ * per block, entries per item and mean time in microseconds.  Allocates
+ * (rebuilds the tables for every candidate): call outside capture. */
+fef_status fef_autotune(fef_plan plan, const void* ops, const double* eps, fef_prec prec,
+                        void* ws, size_t ws_bytes, int32_t reps, void* stream,
+                        int32_t* best_xb, int32_t* best_yc, double* best_us);
+
 const char* fef_status_string(fef_status s);
 
 #ifdef __cplusplus

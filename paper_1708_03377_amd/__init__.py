@@ -7,7 +7,8 @@ device buffers of one fragment system.
 from . import _fef  # noqa: F401
 from ._fef import (PREC, FefError, fef_coulomb_field, fef_half_transform,  # noqa: F401
                    fef_pair_energies, fef_plan_create, fef_plan_get_tiles, fef_plan_query,
-                   fef_plan_set_tiles, fef_scf_step,
+                   fef_plan_set_tiles, fef_scf_step, fef_graph_create, fef_graph_launch,
+                   fef_autotune,
                    fef_status_string, load_library)
 
 

@@ -35,7 +35,8 @@ Q_NSLOT, Q_NENTRIES = 13, 14
 ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_plan_set_tiles", "fef_plan_get_tiles",
                 "fef_half_transform", "fef_pair_energies", "fef_coulomb_field",
-                "fef_scf_step", "fef_status_string")
+                "fef_scf_step", "fef_graph_create", "fef_graph_launch", "fef_graph_destroy",
+                "fef_autotune", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -51,6 +52,12 @@ class SystemDesc(ctypes.Structure):
                 ("npair", ctypes.c_int64),
                 ("pair_x", ctypes.c_void_p), ("pair_y", ctypes.c_void_p),
                 ("pair_s", ctypes.c_void_p)]
+
+
+class PassArgs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("B", "G", "F0", "htilde", "C0", "eps0", "C", "eps", "D", "dD_max", "flags",
+                 "ops", "E2_pair", "E2_total", "ws")] + [("ws_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -76,6 +83,11 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_pair_energies.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.fef_coulomb_field.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fef_scf_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_graph_create.argtypes = [vp, ctypes.POINTER(PassArgs), i32, i32, ctypes.POINTER(vp)]
+    lib.fef_graph_launch.argtypes = [vp, vp]
+    lib.fef_graph_destroy.argtypes = [vp]
+    lib.fef_autotune.argtypes = [vp, vp, vp, i32, vp, sz, i32, vp, ctypes.POINTER(i32),
+                                 ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.fef_status_string.argtypes = [i32]
     lib.fef_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -191,3 +203,41 @@ def fef_scf_step(plan, B, G, F0, htilde, C, eps, D, dD_max, flags, ws, stream=No
     _check("fef_scf_step", load_library().fef_scf_step(
         plan.handle, _ptr(B), _ptr(G), _ptr(F0), _ptr(htilde), _ptr(C), _ptr(eps), _ptr(D),
         _ptr(dD_max), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+class Graph:
+    """Owns a fef_graph handle (and references to the buffers it bakes in)."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            try:
+                load_library().fef_graph_destroy(self.handle)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def fef_graph_create(plan, niter, prec, B, G, F0, htilde, C0, eps0, C, eps, D, dD_max, flags,
+                     ops, E2_pair, E2_total, ws) -> Graph:
+    bufs = (B, G, F0, htilde, C0, eps0, C, eps, D, dD_max, flags, ops, E2_pair, E2_total, ws)
+    a = PassArgs(*[_ptr(t) for t in bufs], _nbytes(ws))
+    h = ctypes.c_void_p()
+    _check("fef_graph_create", load_library().fef_graph_create(plan.handle, ctypes.byref(a),
+                                                               niter, prec, ctypes.byref(h)))
+    return Graph(h.value, (plan, bufs))
+
+
+def fef_graph_launch(graph: Graph, stream=None):
+    _check("fef_graph_launch", load_library().fef_graph_launch(graph.handle, _stream(stream)))
+
+
+def fef_autotune(plan, ops, eps, prec, ws, reps=3, stream=None):
+    xb, yc, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check("fef_autotune", load_library().fef_autotune(
+        plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(ws), _nbytes(ws), reps, _stream(stream),
+        ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us)))
+    return xb.value, yc.value, us.value

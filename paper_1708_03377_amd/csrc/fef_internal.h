@@ -151,6 +151,9 @@ void order_and_orient(fef_plan_s& p);
 hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc);
 void free_tiles(fef::TileSet& t);
 
+// Compute units of the current device (queried once, cached).
+int compute_units();
+
 // One-time kernel attributes (dynamic LDS above 64 KB).
 void configure_split_kernels(int pw);
 void configure_plain_kernels(int kpad64, int kpad32);

@@ -220,16 +220,21 @@ hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double
                               fef_prec prec, double* partial, int32_t* head, int grid,
                               hipStream_t st);
 
-static int persistent_grid(int64_t nitems, int per_cu) {
+int compute_units() {
   static int ncu = 0;
   if (ncu == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        ncu <= 0)
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      ncu = n;
+    else
       ncu = 256;
   }
-  const int64_t g = (int64_t)ncu * per_cu;
+  return ncu;
+}
+
+static int persistent_grid(int64_t nitems, int per_cu) {
+  const int64_t g = (int64_t)compute_units() * per_cu;
   return (int)(nitems < g ? nitems : g);
 }
 

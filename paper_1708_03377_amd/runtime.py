@@ -88,6 +88,25 @@ class Context:
         for _ in range(niter):
             self.scf_step()
 
+    def graph(self, niter: int, prec: int, from_start: bool = True):
+        """A captured FEF pass: [reset to the generated orbitals], niter SCF
+        steps, half transform and pair energies in mode ``prec``."""
+        return F.fef_graph_create(self.plan, niter, prec, self.B, self.G, self.F0, self.htilde,
+                                  self.C0 if from_start else None,
+                                  self.eps0 if from_start else None, self.C, self.eps, self.D,
+                                  self.dD_max, self.flags, self.ops_for(prec), self.E2_pair,
+                                  self.E2_total, self.ws)
+
+    def launch(self, graph):
+        F.fef_graph_launch(graph, self.stream())
+
+    def autotune(self, prec: int, reps: int = 3):
+        """Picks the fastest pair-kernel tiling for the current operands
+        (runs the half transform first)."""
+        self.half_transform(prec)
+        return F.fef_autotune(self.plan, self.ops_for(prec), self.eps, prec, self.ws, reps,
+                              self.stream())
+
     def energies(self, prec: int):
         """Half transform + pair energies on the current orbitals."""
         self.half_transform(prec)

@@ -205,3 +205,37 @@ def test_tilings_agree(torch, prec, tiles):
             assert lib.fef_plan_get_tiles(ctx.plan, PREC[prec]) == (xb, yc)
             got = ctx.pair_energies(PREC[prec])[0].cpu().numpy()
             np.testing.assert_allclose(got, base, rtol=1e-12 if prec == "f64" else 1e-6, atol=0)
+
+
+def test_graph_replays_match_eager(torch):
+    """A captured FEF pass replays bitwise like the eager calls, also with
+    eager work and synchronisations between replays."""
+    import paper_1708_03377_amd as lib
+    for sysm, prec in ((fefgen.make_system(0), "f64"), (two_class_system(), "bf16x2")):
+        ctx = ctx_for(sysm)
+        p = PREC[prec]
+        ctx.reset_orbitals(); ctx.scf(3)
+        E_eager = ctx.energies(p)[0].cpu().numpy().copy()
+        C_eager = ctx.C.cpu().numpy().copy()
+        g = ctx.graph(3, p)
+        for rep in range(3):
+            ctx.E2_pair.fill_(0.0); ctx.C.fill_(0.0)
+            ctx.launch(g)
+            torch.cuda.synchronize()
+            assert np.array_equal(ctx.E2_pair[:ctx.npair].cpu().numpy(), E_eager), rep
+            assert np.array_equal(ctx.C.cpu().numpy(), C_eager), rep
+            ctx.pair_energies(p)  # eager work between replays
+            torch.cuda.synchronize()
+
+
+def test_autotune_keeps_results(torch):
+    import paper_1708_03377_amd as lib
+    sysm = fefgen.make_system(0)
+    ref, _ = ofef.pair_energies(sysm)
+    ctx = ctx_for(sysm)
+    for prec in ("f64", "fp16x2"):
+        xb, yc, us = ctx.autotune(PREC[prec], reps=2)
+        assert lib.fef_plan_get_tiles(ctx.plan, PREC[prec]) == (xb, yc)
+        assert us > 0
+        E2 = ctx.pair_energies(PREC[prec])[0].cpu().numpy()
+        assert np.max(np.abs(E2 - ref)) <= (TOL_PAIR_F64 if prec == "f64" else 1e-6)
