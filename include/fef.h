@@ -209,7 +209,8 @@ typedef struct {
 
 typedef struct fef_graph_s* fef_graph;
 
-/* Records one whole FEF pass -- [reset of C, eps], niter SCF steps
+/* Records one whole FEF pass -- clearing of flags, [reset of C, eps],
+ * niter SCF steps
  * (fef_scf_step), the half transform and the pair energies in mode `prec`
  * -- into a HIP graph (stream capture on a private default-priority stream;
  * no allocation happens during replay).  Call outside any capture; the plan

@@ -19,6 +19,8 @@ __global__ void copy_kernel(const double* __restrict__ src, double* __restrict__
     dst[i] = src[i];
 }
 
+__global__ void zero_flags_kernel(int32_t* flags) { *flags = 0; }
+
 }  // namespace fef
 
 using namespace fef;
@@ -45,6 +47,8 @@ fef_status fef_graph_create(fef_plan p, const fef_pass_args* a, int32_t niter, f
   fef_status status = FEF_OK;
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) status = FEF_E_HIP;
   if (status == FEF_OK) {
+    // each replay reports its own flags (a fill kernel, not a memset node)
+    hipLaunchKernelGGL(zero_flags_kernel, dim3(1), dim3(1), 0, st, a->flags);
     if (a->C0 && p->nC > 0) {
       hipLaunchKernelGGL(copy_kernel, dim3(256), dim3(256), 0, st, a->C0, a->C, p->nC);
       hipLaunchKernelGGL(copy_kernel, dim3(64), dim3(256), 0, st, a->eps0, a->eps, p->nEps);
@@ -106,8 +110,8 @@ fef_status fef_autotune(fef_plan p, const void* ops, const double* eps, fef_prec
     for (int xb : {2, 4})
       for (int yc : ycs) cand.push_back({xb, yc});
   }
-  // scratch outputs live at the end of the caller's workspace is not
-  // possible (it is the pair workspace); the library owns two scratch words
+  // the candidates write their results into library-owned scratch, so the
+  // caller's E2_pair / E2_total keep their contents
   double* e2 = nullptr;
   double* tot = nullptr;
   int32_t* flags = nullptr;
