@@ -323,12 +323,14 @@ def assemble(frags: List[tuple], cls: Sequence[int], naux_class: Sequence[int],
 
 
 def make_system(cfg, extra_seed: Sequence[int] = (), n_water: Optional[int] = None,
-                cutoff: Optional[float] = "cfg") -> System:
+                cutoff: Optional[float] = "cfg", coupling_of: Optional[int] = None) -> System:
     """Build the seeded system for a workload ``cfg`` (id or Spec).
 
     ``extra_seed`` appends entries to the root seed (independent boxes of the
     same style, e.g. surrogate training boxes); ``n_water`` shrinks or grows the
-    box at the same density; ``cutoff`` overrides the pair cutoff.
+    box at the same density; ``cutoff`` overrides the pair cutoff;
+    ``coupling_of`` takes the class coupling G from workload ``coupling_of``'s
+    seed stream instead (boxes of the same fragment type share one coupling).
     """
     spec = CONFIGS[cfg] if isinstance(cfg, int) else cfg
     if n_water is not None:
@@ -341,6 +343,10 @@ def make_system(cfg, extra_seed: Sequence[int] = (), n_water: Optional[int] = No
     rng_pos = np.random.default_rng(kids[0])
     rng_G = np.random.default_rng(kids[1])
     rng_Gnb = np.random.default_rng(kids[2])
+    if coupling_of is not None:
+        # child 1 of the workload's own root sequence is its G stream
+        rng_G = np.random.default_rng(
+            np.random.SeedSequence([ROOT_SEED, int(coupling_of)]).spawn(2)[1])
 
     G0 = draw_G(rng_G, WATER["naux"])
     Gs = [G0]
@@ -428,3 +434,61 @@ def make_two_class_system(seed: int, solute: tuple, solvent: Sequence[tuple],
         frags.append((B, C, eps, no))
     return assemble(frags, [1] + [0] * len(solvent), [naux0, p1], [G0, G1], pos,
                     box, cutoff=cutoff)
+
+
+# ---------------------------------------------------------------------------
+# Random draws of the distant-pair surrogate (initial weights, mini-batch
+# orders).  Packing order of one member's parameters: W0[128][17], b0[128],
+# W1[128][128], b1[128], W2[128], b2; members are MLP_STRIDE numbers apart.
+MLP_LAYERS = (17, 128, 128, 1)
+MLP_STRIDE = 18952
+
+
+def mlp_init(seed: int, nmember: int) -> np.ndarray:
+    """Initial FP32 parameters [nmember][MLP_STRIDE]: weights uniform in
+    +-1/sqrt(fan_in), biases zero, each member from its own seed stream."""
+    out = np.zeros((nmember, MLP_STRIDE), dtype=np.float32)
+    for m in range(nmember):
+        rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 7777, seed, m]))
+        o = 0
+        for layer in range(3):
+            fi, fo = MLP_LAYERS[layer], MLP_LAYERS[layer + 1]
+            bound = 1.0 / math.sqrt(fi)
+            out[m, o:o + fo * fi] = rng.uniform(-bound, bound, size=fo * fi)
+            o += fo * fi + fo  # biases stay zero
+    return out
+
+
+def mlp_unpack(flat: np.ndarray) -> dict:
+    """One member's packed parameters as {W0, b0, W1, b1, W2, b2} (views)."""
+    p, o = {}, 0
+    for layer in range(3):
+        fi, fo = MLP_LAYERS[layer], MLP_LAYERS[layer + 1]
+        p[f"W{layer}"] = flat[o:o + fo * fi].reshape(fo, fi)
+        o += fo * fi
+        p[f"b{layer}"] = flat[o:o + fo]
+        o += fo
+    return p
+
+
+def epoch_batches(seed: int, epoch: int, nmember: int, ndata: int, nb: int) -> np.ndarray:
+    """Mini-batch row indices for one epoch, [nsteps][nmember][nb] int32:
+    each member walks its own permutation of the rows (the last partial batch
+    is dropped)."""
+    nsteps = ndata // nb
+    out = np.empty((nsteps, nmember, nb), dtype=np.int32)
+    for m in range(nmember):
+        rng = np.random.default_rng(np.random.SeedSequence([ROOT_SEED, 7778, seed, epoch, m]))
+        perm = rng.permutation(ndata)[:nsteps * nb].astype(np.int32)
+        out[:, m, :] = perm.reshape(nsteps, nb)
+    return out
+
+
+def surrogate_training_box(seed: int, n_water: int = 1000, cutoff: float = 15.0,
+                           coupling_of: int = 4) -> System:
+    """A 1000-water box in the style of workload 1 with the surrogate
+    workload's 15 A cutoff: positions and fragments from its own seed stream
+    (``seed`` >= 100 keeps it apart from every named workload), the water
+    coupling G of workload ``coupling_of`` (the box the surrogate serves)."""
+    return make_system(1, extra_seed=(seed,), n_water=n_water, cutoff=cutoff,
+                       coupling_of=coupling_of)

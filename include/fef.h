@@ -118,12 +118,15 @@ typedef enum {
   FEF_Q_G_ELEMS = 11,       /* doubles in the G pool                     */
   FEF_Q_NPAIR = 12,
   FEF_Q_NSLOT = 13,         /* pair output tiles (partial-sum slots)     */
-  FEF_Q_NENTRIES = 14       /* streamed y tiles of mode `prec`'s tiling   */
+  FEF_Q_NENTRIES = 14,      /* streamed y tiles of mode `prec`'s tiling   */
+  FEF_Q_MASKED_WS_BYTES = 15, /* workspace of fef_pair_energies_masked   */
+  FEF_Q_SURR_WS_BYTES = 16  /* workspace of fef_coupling_modes and
+                               fef_fragment_invariants                  */
 } fef_query;
 
 /* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES,
- * FEF_Q_PAIR_WS_BYTES, FEF_Q_NITEMS and FEF_Q_NENTRIES; it is ignored
- * otherwise. */
+ * FEF_Q_PAIR_WS_BYTES, FEF_Q_NITEMS, FEF_Q_NENTRIES and
+ * FEF_Q_MASKED_WS_BYTES; it is ignored otherwise. */
 fef_status fef_plan_query(fef_plan plan, fef_query what, fef_prec prec,
                           int64_t* out);
 
@@ -231,6 +234,107 @@ fef_status fef_graph_destroy(fef_graph graph);
 fef_status fef_autotune(fef_plan plan, const void* ops, const double* eps, fef_prec prec,
                         void* ws, size_t ws_bytes, int32_t reps, void* stream,
                         int32_t* best_xb, int32_t* best_yc, double* best_us);
+
+/* Pair energies of the selected pairs only (Eqs. ED2, dimDoubles, as
+ * fef_pair_energies): select [npair] device int32, nonzero = evaluate.
+ * E2_pair of an unselected pair keeps the value the caller put there (for
+ * instance a surrogate prediction); E2_total is then the deterministic sum
+ * of E2_pair over all pairs.  Selected pairs get bitwise the values
+ * fef_pair_energies gives them with the same tiling.  Workspace:
+ * FEF_Q_MASKED_WS_BYTES of mode `prec`. */
+fef_status fef_pair_energies_masked(fef_plan plan, const void* ops, const double* eps,
+                                    fef_prec prec, const int32_t* select, double* E2_pair,
+                                    double* E2_total, int32_t* flags, void* ws,
+                                    size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Distant-pair surrogate.  A project addition: the paper has no learned
+ * component.  It predicts E2_xy of Eq. ED2 for distant pairs from
+ * rotation-invariant scalars of the Coulomb moments d^x = B^x : D^x (the
+ * moments that carry the effective field of Eqs. wc and dp2e); the exact
+ * pair kernel (fef_pair_energies_masked) evaluates every pair the surrogate
+ * declines, so it stays both the fallback and the judge of the error.
+ *
+ * Network: 17 -> 128 -> 128 -> 1 with SiLU after the two hidden layers.
+ * Parameters of one member, packed in this order:
+ *   W0[128][17], b0[128], W1[128][128], b1[128], W2[128], b2
+ * (FEF_MLP_NPARAM numbers; members are FEF_MLP_STRIDE elements apart).
+ * FP32 master copies (P, Adam moments M, V) and a BF16 copy W (uint16
+ * bit patterns, round to nearest even) are kept; inference and training
+ * both evaluate the network on W.
+ * Statistics `stats` [FEF_MLP_NSTATS] floats: feature means [17], inverse
+ * feature standard deviations [17], target mean, target standard deviation.
+ * The network sees (x - mean) * inv and predicts (t - tmean) / tstd with
+ * t = E2_xy R_xy^2 (R in bohr).
+ * ------------------------------------------------------------------------ */
+#define FEF_MLP_NIN 17
+#define FEF_MLP_NHID 128
+#define FEF_MLP_NPARAM 18945
+#define FEF_MLP_STRIDE 18952
+#define FEF_MLP_NSTATS 36
+
+/* Q [4][P_0] (device out): eigenvectors of G_{0,0} for its four largest
+ * eigenvalues, largest first (each column's sign is arbitrary).  FP64 Jacobi
+ * on the device.  Workspace: FEF_Q_SURR_WS_BYTES. */
+fef_status fef_coupling_modes(fef_plan plan, const double* G, double* Q, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* U [nfrag][8] (device out): for each class-0 fragment, with its moments
+ * d_P = sum_{mu nu} B[P][mu][nu] D[mu][nu] (D as from fef_scf_step):
+ * U = [d.G^k.d for k = 0..3, (Q_k.d)^2 for k = 0..3], G = G_{0,0}.  Other
+ * classes get NaN (their pairs are always evaluated exactly).  Workspace:
+ * FEF_Q_SURR_WS_BYTES. */
+fef_status fef_fragment_invariants(fef_plan plan, const double* B, const double* G,
+                                   const double* D, const double* Q, double* U, void* ws,
+                                   size_t ws_bytes, void* stream);
+
+/* X [n][17] floats (device out) for the pairs idx [n] (device int32; NULL =
+ * pairs 0..n-1): [R_xy, U^x + U^y (8), U^x * U^y (8)] (symmetric in x, y).
+ * With E2_pair and T non-NULL also the targets T[q] = E2_pair[idx[q]] R^2. */
+fef_status fef_pair_features(fef_plan plan, const double* U, const double* E2_pair,
+                             const int32_t* idx, int64_t n, float* X, float* T,
+                             void* stream);
+
+/* Per-column mean and standard deviation (inverse != 0: its inverse) of a
+ * row-major [n][ncol] float matrix, FP64 two-pass, fixed summation order. */
+fef_status fef_column_stats(int64_t n, int32_t ncol, int32_t inverse, const float* A,
+                            float* mean, float* sdev, void* stream);
+
+/* W = BF16(P) for nmember members (device pointers, FEF_MLP_STRIDE apart). */
+fef_status fef_mlp_pack(int32_t nmember, const float* P, uint16_t* W, void* stream);
+
+/* Y [nmember][n] (device out): standardised predictions of every member for
+ * the rows of X [n][17] (raw features).  MFMA BF16, FP32 accumulation. */
+fef_status fef_mlp_forward(int32_t nmember, int64_t n, const float* X, const float* stats,
+                           const uint16_t* W, float* Y, void* stream);
+
+/* One training step of every member on its own mini-batch: rows
+ * idx [nmember][nb] (device int32) of X [*][17] with targets T [*] (raw).
+ * Mean squared error of the standardised targets; gradients in FP32 on the
+ * BF16 weights W, summed over the batch in a fixed order; Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected step `step` >= 1, rate lr) on the
+ * FP32 masters P, M, V, then W = BF16(P).  step = 0 computes gradients and
+ * loss only.  loss [nmember] and grad [nmember][FEF_MLP_STRIDE] (device,
+ * nullable) receive the batch loss and the gradient.  Workspace bytes from
+ * fef_mlp_train_ws_bytes. */
+fef_status fef_mlp_train_step(int32_t nmember, const float* X, const float* T,
+                              const int32_t* idx, int32_t nb, const float* stats, float* P,
+                              float* M, float* V, uint16_t* W, int32_t step, float lr,
+                              float* loss, float* grad, void* ws, size_t ws_bytes,
+                              void* stream);
+fef_status fef_mlp_train_ws_bytes(int32_t nmember, int32_t nb, int64_t* out);
+
+/* Surrogate selection over every pair of the plan: the ensemble (nmember
+ * members, features from U) predicts E2_xy = (mean * tstd + tmean) / R^2;
+ * a pair is sent to the exact kernel (select = 1, E2_pair = 0) when
+ * R < r_exact (bohr), when the members' spread (max - min) in Eh exceeds
+ * `threshold`, when a fragment is outside class 0 or the prediction is not
+ * finite; otherwise select = 0 and E2_pair holds the prediction.  Follow with
+ * fef_pair_energies_masked to complete E2_pair and E2_total. */
+fef_status fef_surrogate_select(fef_plan plan, const double* U, int32_t nmember,
+                                const float* stats, const uint16_t* W, double r_exact,
+                                double threshold, double* E2_pair, int32_t* select,
+                                void* stream);
 
 const char* fef_status_string(fef_status s);
 

@@ -29,14 +29,19 @@ PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
 
 Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
-Q_NSLOT, Q_NENTRIES = 13, 14
+Q_NSLOT, Q_NENTRIES, Q_MASKED_WS_BYTES, Q_SURR_WS_BYTES = 13, 14, 15, 16
+
+MLP_NIN, MLP_NHID, MLP_NPARAM, MLP_STRIDE, MLP_NSTATS = 17, 128, 18945, 18952, 36
 
 # every entry point declared in include/fef.h
 ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_plan_set_tiles", "fef_plan_get_tiles",
                 "fef_half_transform", "fef_pair_energies", "fef_coulomb_field",
                 "fef_scf_step", "fef_graph_create", "fef_graph_launch", "fef_graph_destroy",
-                "fef_autotune", "fef_status_string")
+                "fef_autotune", "fef_pair_energies_masked", "fef_coupling_modes",
+                "fef_fragment_invariants", "fef_pair_features", "fef_column_stats",
+                "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
+                "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -88,6 +93,18 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_graph_destroy.argtypes = [vp]
     lib.fef_autotune.argtypes = [vp, vp, vp, i32, vp, sz, i32, vp, ctypes.POINTER(i32),
                                  ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    f32, f64 = ctypes.c_float, ctypes.c_double
+    lib.fef_pair_energies_masked.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_coupling_modes.argtypes = [vp, vp, vp, vp, sz, vp]
+    lib.fef_fragment_invariants.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_pair_features.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.fef_column_stats.argtypes = [i64, i32, i32, vp, vp, vp, vp]
+    lib.fef_mlp_pack.argtypes = [i32, vp, vp, vp]
+    lib.fef_mlp_forward.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+    lib.fef_mlp_train_step.argtypes = [i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, i32, f32, vp,
+                                       vp, vp, sz, vp]
+    lib.fef_mlp_train_ws_bytes.argtypes = [i32, i32, ctypes.POINTER(i64)]
+    lib.fef_surrogate_select.argtypes = [vp, vp, i32, vp, vp, f64, f64, vp, vp, vp]
     lib.fef_status_string.argtypes = [i32]
     lib.fef_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -241,3 +258,62 @@ def fef_autotune(plan, ops, eps, prec, ws, reps=3, stream=None):
         plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(ws), _nbytes(ws), reps, _stream(stream),
         ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us)))
     return xb.value, yc.value, us.value
+
+
+def fef_pair_energies_masked(plan, ops, eps, prec, select, E2_pair, E2_total, flags, ws,
+                             stream=None):
+    _check("fef_pair_energies_masked", load_library().fef_pair_energies_masked(
+        plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(select), _ptr(E2_pair), _ptr(E2_total),
+        _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_coupling_modes(plan, G, Q, ws, stream=None):
+    _check("fef_coupling_modes", load_library().fef_coupling_modes(
+        plan.handle, _ptr(G), _ptr(Q), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_fragment_invariants(plan, B, G, D, Q, U, ws, stream=None):
+    _check("fef_fragment_invariants", load_library().fef_fragment_invariants(
+        plan.handle, _ptr(B), _ptr(G), _ptr(D), _ptr(Q), _ptr(U), _ptr(ws), _nbytes(ws),
+        _stream(stream)))
+
+
+def fef_pair_features(plan, U, E2_pair, idx, n, X, T, stream=None):
+    _check("fef_pair_features", load_library().fef_pair_features(
+        plan.handle, _ptr(U), _ptr(E2_pair), _ptr(idx), n, _ptr(X), _ptr(T), _stream(stream)))
+
+
+def fef_column_stats(n, ncol, inverse, A, mean, sdev, stream=None):
+    _check("fef_column_stats", load_library().fef_column_stats(
+        n, ncol, int(inverse), _ptr(A), _ptr(mean), _ptr(sdev), _stream(stream)))
+
+
+def fef_mlp_pack(nmember, P, W, stream=None):
+    _check("fef_mlp_pack", load_library().fef_mlp_pack(nmember, _ptr(P), _ptr(W),
+                                                       _stream(stream)))
+
+
+def fef_mlp_forward(nmember, n, X, stats, W, Y, stream=None):
+    _check("fef_mlp_forward", load_library().fef_mlp_forward(
+        nmember, n, _ptr(X), _ptr(stats), _ptr(W), _ptr(Y), _stream(stream)))
+
+
+def fef_mlp_train_ws_bytes(nmember, nb) -> int:
+    out = ctypes.c_int64()
+    _check("fef_mlp_train_ws_bytes", load_library().fef_mlp_train_ws_bytes(
+        nmember, nb, ctypes.byref(out)))
+    return out.value
+
+
+def fef_mlp_train_step(nmember, X, T, idx, nb, stats, P, M, V, W, step, lr, loss, grad, ws,
+                       stream=None):
+    _check("fef_mlp_train_step", load_library().fef_mlp_train_step(
+        nmember, _ptr(X), _ptr(T), _ptr(idx), nb, _ptr(stats), _ptr(P), _ptr(M), _ptr(V),
+        _ptr(W), step, lr, _ptr(loss), _ptr(grad), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_surrogate_select(plan, U, nmember, stats, W, r_exact, threshold, E2_pair, select,
+                         stream=None):
+    _check("fef_surrogate_select", load_library().fef_surrogate_select(
+        plan.handle, _ptr(U), nmember, _ptr(stats), _ptr(W), float(r_exact), float(threshold),
+        _ptr(E2_pair), _ptr(select), _stream(stream)))

@@ -27,7 +27,7 @@ void free_plan(fef_plan_s* p) {
   void* ptrs[] = {p->d_frag, p->d_pair, p->d_slot_pair, p->d_ht, p->d_ht_fused, p->d_ht_generic,
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
-                  p->d_eig_mid, p->d_eig_large};
+                  p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -72,13 +72,29 @@ int64_t pair_ws_bytes(const fef_plan_s& p, fef_prec) {
          round_up(round_up(std::max<int64_t>(p.nGap, 1), 32) * (int64_t)sizeof(double), 256) +
          256 * (int64_t)sizeof(double);
 }
-static int64_t naux_total(const fef_plan_s& p) {
+int64_t naux_total(const fef_plan_s& p) {
   int64_t t = 0;
   for (const auto& f : p.frag) t += f.naux;
   return t;
 }
 int64_t field_ws_bytes(const fef_plan_s& p) {
   return round_up(2 * std::max<int64_t>(naux_total(p), 1) * (int64_t)sizeof(double), 256);
+}
+// pair workspace, then the masked copies of the entries and work items
+int64_t masked_ws_bytes(const fef_plan_s& p, fef_prec prec) {
+  const TileSet& t = p.tiles[prec];
+  return pair_ws_bytes(p, prec) +
+         round_up(std::max<int64_t>(t.nentries, 1) * (int64_t)sizeof(Entry), 256) +
+         round_up(std::max<int64_t>(t.nitems, 1) * (int64_t)sizeof(WorkItem), 256);
+}
+// coupling modes: V, eps, Dnew, Dold [P0^2 or P0], max, flags, two Jacobi
+// slots; invariants: the moments [sum P_c]
+int64_t surr_ws_bytes(const fef_plan_s& p) {
+  const int64_t n = p.P0;
+  const int64_t modes = (3 * n * n + n + 2) * (int64_t)sizeof(double) + 256 +
+                        2 * (n + 1) * (n + 1) * (int64_t)sizeof(double) + 4 * 256;
+  const int64_t inv = round_up(std::max<int64_t>(naux_total(p), 1) * (int64_t)sizeof(double), 256);
+  return std::max(modes, inv);
 }
 int64_t scf_ws_bytes(const fef_plan_s& p) {
   const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
@@ -263,6 +279,14 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   if (e == hipSuccess) e = upload(&p->d_eig_small, p->eig_small);
   if (e == hipSuccess) e = upload(&p->d_eig_mid, p->eig_mid);
   if (e == hipSuccess) e = upload(&p->d_eig_large, p->eig_large);
+  if (e == hipSuccess) {
+    FragInfo g;
+    std::memset(&g, 0, sizeof(g));
+    g.nbf = p->P0;
+    g.naux = 1;
+    e = upload(&p->d_gfrag, std::vector<FragInfo>{g});
+  }
+  if (e == hipSuccess) e = upload(&p->d_glist, std::vector<int32_t>{0});
   if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
   *out = p;
   return FEF_OK;
@@ -278,7 +302,7 @@ fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* ou
   if (!p || !out) return FEF_E_ARG;
   const bool needs_prec = what == FEF_Q_OPS_BYTES || what == FEF_Q_HALF_WS_BYTES ||
                           what == FEF_Q_PAIR_WS_BYTES || what == FEF_Q_NITEMS ||
-                          what == FEF_Q_NENTRIES;
+                          what == FEF_Q_NENTRIES || what == FEF_Q_MASKED_WS_BYTES;
   if (needs_prec && !valid_prec(prec)) return FEF_E_PREC;
   switch (what) {
     case FEF_Q_OPS_BYTES: *out = p->ops_bytes[prec]; break;
@@ -296,6 +320,8 @@ fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* ou
     case FEF_Q_NPAIR: *out = p->npair; break;
     case FEF_Q_NSLOT: *out = p->nslot; break;
     case FEF_Q_NENTRIES: *out = p->tiles[prec].nentries; break;
+    case FEF_Q_MASKED_WS_BYTES: *out = masked_ws_bytes(*p, prec); break;
+    case FEF_Q_SURR_WS_BYTES: *out = surr_ws_bytes(*p); break;
     default: return FEF_E_ARG;
   }
   return FEF_OK;
@@ -343,7 +369,7 @@ fef_status fef_pair_energies(fef_plan p, const void* ops, const double* eps, fef
   if (!E2_total || !flags) return FEF_E_ARG;
   if (p->npair > 0 && (!ops || !eps || !E2_pair)) return FEF_E_ARG;
   if ((int64_t)ws_bytes < pair_ws_bytes(*p, prec) || !ws) return FEF_E_WORKSPACE;
-  return hip_status(launch_pair_energies(*p, ops, eps, prec, E2_pair, E2_total, flags, ws,
+  return hip_status(launch_pair_energies(*p, ops, eps, prec, nullptr, E2_pair, E2_total, flags, ws,
                                          static_cast<hipStream_t>(stream)));
 }
 

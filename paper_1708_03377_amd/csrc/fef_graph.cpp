@@ -129,12 +129,12 @@ fef_status fef_autotune(fef_plan p, const void* ops, const double* eps, fef_prec
   fef_status status = FEF_OK;
   for (const auto& c : cand) {
     if (build_tiles(*p, prec, c.first, c.second) != hipSuccess) { status = FEF_E_HIP; break; }
-    if (launch_pair_energies(*p, ops, eps, prec, e2, tot, flags, ws, st) != hipSuccess) {
+    if (launch_pair_energies(*p, ops, eps, prec, nullptr, e2, tot, flags, ws, st) != hipSuccess) {
       status = FEF_E_HIP;
       break;
     }
     (void)hipEventRecord(t0, st);
-    for (int r = 0; r < reps; ++r) (void)launch_pair_energies(*p, ops, eps, prec, e2, tot, flags, ws, st);
+    for (int r = 0; r < reps; ++r) (void)launch_pair_energies(*p, ops, eps, prec, nullptr, e2, tot, flags, ws, st);
     (void)hipEventRecord(t1, st);
     (void)hipEventSynchronize(t1);
     float ms = 0.0f;

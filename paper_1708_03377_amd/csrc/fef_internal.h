@@ -124,6 +124,9 @@ struct fef_plan_s {
   int32_t* d_eig_mid = nullptr;
   int32_t* d_eig_large = nullptr;
   int64_t nbr_total = 0;
+  // G_{0,0} posed as one "fragment" for the eigensolver (coupling modes)
+  fef::FragInfo* d_gfrag = nullptr;
+  int32_t* d_glist = nullptr;
 };
 
 namespace fef {
@@ -135,8 +138,8 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
 hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const double* w,
                              void* ops, fef_prec prec, hipStream_t st);
 hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const double* eps,
-                                fef_prec prec, double* E2_pair, double* E2_total,
-                                int32_t* flags, void* ws, hipStream_t st);
+                                fef_prec prec, const int32_t* select, double* E2_pair,
+                                double* E2_total, int32_t* flags, void* ws, hipStream_t st);
 hipError_t launch_density(const fef_plan_s& p, const double* C, double* D,
                           double* dD_max, hipStream_t st);
 hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
@@ -145,6 +148,32 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* C, double* eps, double* Dnew, double* dD_max,
                        int32_t* flags, double* ws_eig, hipStream_t st);
+hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, const double* F,
+                           const double* Dold, double* C, double* eps, double* Dnew,
+                           double* dmax, int32_t* flags, double* ws_eig, hipStream_t st);
+hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
+                          hipStream_t st);
+
+// Surrogate (k_mlp.hip).
+hipError_t launch_top_modes(const double* V, int n, double* Q, hipStream_t st);
+hipError_t launch_invariants(const fef_plan_s& p, const double* dmom, const double* G,
+                             const double* Q, double* U, hipStream_t st);
+hipError_t launch_features(const fef_plan_s& p, const double* U, const double* E2,
+                           const int32_t* idx, int64_t n, float* X, float* T, hipStream_t st);
+hipError_t launch_column_stats(int64_t n, int ncol, int inverse, const float* A, float* mean,
+                               float* sdev, hipStream_t st);
+hipError_t launch_mlp_pack(int nmember, const float* P, uint16_t* W, hipStream_t st);
+hipError_t launch_mlp_forward(int nmember, int64_t n, const float* X, const float* stats,
+                              const uint16_t* W, float* Y, hipStream_t st);
+hipError_t launch_surrogate_select(const fef_plan_s& p, const double* U, int nmember,
+                                   const float* stats, const uint16_t* W, double r_exact,
+                                   double thr, double* E2_pair, int32_t* select, float* Y,
+                                   hipStream_t st);
+int64_t mlp_train_ws_bytes(int nmember, int32_t nb);
+hipError_t launch_mlp_train_step(int nmember, const float* X, const float* T, const int32_t* idx,
+                                 int32_t nb, const float* stats, float* P, float* M, float* V,
+                                 uint16_t* W, int32_t step, float lr, float* loss, float* grad,
+                                 void* ws, hipStream_t st);
 
 // Pair-kernel tiling (fef_tiles.cpp).
 void order_and_orient(fef_plan_s& p);
@@ -163,5 +192,8 @@ int64_t half_ws_bytes(const fef_plan_s& p, fef_prec prec);
 int64_t pair_ws_bytes(const fef_plan_s& p, fef_prec prec);
 int64_t field_ws_bytes(const fef_plan_s& p);
 int64_t scf_ws_bytes(const fef_plan_s& p);
+int64_t masked_ws_bytes(const fef_plan_s& p, fef_prec prec);
+int64_t surr_ws_bytes(const fef_plan_s& p);
+int64_t naux_total(const fef_plan_s& p);
 
 }  // namespace fef

@@ -331,4 +331,14 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
   return hipGetLastError();
 }
 
+// One matrix n x n (for instance the coupling G_00 posed as a fragment with
+// no occupied orbitals), global-memory path, cold start.
+hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, const double* F,
+                           const double* Dold, double* C, double* eps, double* Dnew,
+                           double* dmax, int32_t* flags, double* ws_eig, hipStream_t st) {
+  hipLaunchKernelGGL((eigh_kernel<1024, 0>), dim3(1), dim3(1024), eig_scratch_bytes(n), st, d_fi,
+                     d_list, F, Dold, C, eps, Dnew, dmax, flags, ws_eig, n);
+  return hipGetLastError();
+}
+
 }  // namespace fef

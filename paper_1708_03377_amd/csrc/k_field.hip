@@ -140,6 +140,13 @@ hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, doubl
   return hipGetLastError();
 }
 
+hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 3) / 4), dim3(256), 0, st,
+                     p.d_frag, B, D, dmom);
+  return hipGetLastError();
+}
+
 hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G, const double* D,
                         const double* F0, const double* htilde, double* out, double* ws_d,
                         double* ws_phi, hipStream_t st) {

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
     __syncthreads();
     if (it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
+    if (ne == 0) continue;  // an item emptied by a pair mask
     const int fxi = xblocks[xbid].f[0];
     const int mt = xblocks[xbid].mt[0];
     {
@@ -145,6 +146,33 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
 
 __global__ void reset_head_kernel(int32_t* head) { *head = 0; }
 
+// Pair mask: copies every work item's entries, in order, into the same
+// positions of a second table, keeping only the units whose pair is selected
+// and dropping entries left with none; the item keeps its x-block and start
+// and gets the new length (possibly 0).
+__global__ void mask_items_kernel(const WorkItem* __restrict__ items, int32_t nitems,
+                                  const Entry* __restrict__ entries,
+                                  const int32_t* __restrict__ slot_pair,
+                                  const int32_t* __restrict__ select,
+                                  Entry* __restrict__ out_entries,
+                                  WorkItem* __restrict__ out_items) {
+  const int32_t it = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (it >= nitems) return;
+  const WorkItem w = items[it];
+  int32_t k = 0;
+  for (int32_t e = w.e0; e < w.e0 + w.ne; ++e) {
+    Entry en = entries[e];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kMaxXB; ++u) {
+      if (en.slot[u] >= 0 && !select[slot_pair[en.slot[u]]]) en.slot[u] = -1;
+      any |= en.slot[u] >= 0;
+    }
+    if (any) out_entries[w.e0 + k++] = en;
+  }
+  out_items[it] = WorkItem{w.xblock, w.e0, k, 0};
+}
+
 // Delta_ia = eps_i - eps_a for every fragment, -1 on the padding up to ld;
 // raises the gap flag for a non-negative Delta.
 __global__ __launch_bounds__(256) void gaps_kernel(const FragInfo* __restrict__ frag,
@@ -181,12 +209,15 @@ void configure_plain_kernels(int kpad64, int kpad32) {
   (void)hipGetLastError();
 }
 
-// E2_pair[p] = sum of the pair's tile partials, in slot order.
+// E2_pair[p] = sum of the pair's tile partials, in slot order; with a mask,
+// only the selected pairs are written.
 __global__ void pair_reduce_kernel(const PairInfo* __restrict__ pairs, int64_t npair,
                                    const double* __restrict__ partial,
+                                   const int32_t* __restrict__ select,
                                    double* __restrict__ E2_pair, int32_t* __restrict__ flags) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npair) return;
+  if (select && !select[p]) return;
   const PairInfo pr = pairs[p];
   double s = 0.0;
   for (int k = 0; k < pr.ntx * pr.nty; ++k) s += partial[pr.slot_first + k];
@@ -217,8 +248,8 @@ __global__ __launch_bounds__(256) void total_stage2_kernel(const double* __restr
 }
 
 hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
-                              fef_prec prec, double* partial, int32_t* head, int grid,
-                              hipStream_t st);
+                              fef_prec prec, const Entry* entries, const WorkItem* items,
+                              double* partial, int32_t* head, int grid, hipStream_t st);
 
 int compute_units() {
   static int ncu = 0;
@@ -239,14 +270,27 @@ static int persistent_grid(int64_t nitems, int per_cu) {
 }
 
 hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const double* eps,
-                                fef_prec prec, double* E2_pair, double* E2_total,
-                                int32_t* flags, void* ws, hipStream_t st) {
+                                fef_prec prec, const int32_t* select, double* E2_pair,
+                                double* E2_total, int32_t* flags, void* ws, hipStream_t st) {
   double* partial = static_cast<double*>(ws);
   char* wsb = static_cast<char*>(ws) + round_up(std::max<int64_t>(p.nslot, 1) * (int64_t)sizeof(double), 256);
   int32_t* head = reinterpret_cast<int32_t*>(wsb);
   double* gap = reinterpret_cast<double*>(wsb + 256);
   const char* o = static_cast<const char*>(ops);
   const TileSet& t = p.tiles[prec];
+  const Entry* entries = t.d_entries;
+  const WorkItem* items = t.d_items;
+  if (select && t.nitems > 0) {
+    char* mb = static_cast<char*>(ws) + pair_ws_bytes(p, prec);
+    Entry* me = reinterpret_cast<Entry*>(mb);
+    WorkItem* mi = reinterpret_cast<WorkItem*>(
+        mb + round_up(std::max<int64_t>(t.nentries, 1) * (int64_t)sizeof(Entry), 256));
+    hipLaunchKernelGGL(mask_items_kernel, dim3((unsigned)((t.nitems + 255) / 256)), dim3(256), 0,
+                       st, t.d_items, (int32_t)t.nitems, t.d_entries, p.d_slot_pair, select, me,
+                       mi);
+    entries = me;
+    items = mi;
+  }
   if (t.nitems > 0) {
     hipLaunchKernelGGL(reset_head_kernel, dim3(1), dim3(1), 0, st, head);
     hipLaunchKernelGGL(gaps_kernel, dim3(p.nfrag), dim3(256), 0, st, p.d_frag, eps, gap, flags);
@@ -259,7 +303,7 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
         const size_t lds = 2 * (size_t)kpad * kTile * (f64 ? sizeof(double) : sizeof(float));
 #define FEF_PLAIN(T, KS)                                                                        \
   hipLaunchKernelGGL((pair_plain_kernel<T, KS>), grid, dim3(256), lds, st, p.d_frag, p.d_pair,  \
-                     p.d_slot_pair, t.d_xblocks, t.d_entries, t.d_items, (int32_t)t.nitems,     \
+                     p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,             \
                      head, o, (int)prec, kpad, gap, partial)
         if (f64) {
           if (kpad == 72) FEF_PLAIN(double, 18); else if (kpad == 8) FEF_PLAIN(double, 2);
@@ -272,7 +316,7 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
         break;
       }
       default: {
-        hipError_t e = launch_split_pairs(p, ops, gap, prec, partial, head,
+        hipError_t e = launch_split_pairs(p, ops, gap, prec, entries, items, partial, head,
                                           persistent_grid(t.nitems, 1), st);
         if (e != hipSuccess) return e;
       }
@@ -280,7 +324,7 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
   }
   if (p.npair > 0)
     hipLaunchKernelGGL(pair_reduce_kernel, dim3((unsigned)((p.npair + 255) / 256)), dim3(256), 0,
-                       st, p.d_pair, p.npair, partial, E2_pair, flags);
+                       st, p.d_pair, p.npair, partial, select, E2_pair, flags);
   double* tpart = gap + round_up(std::max<int64_t>(p.nGap, 1), 32);
   hipLaunchKernelGGL(total_stage1_kernel, dim3(kTotalBlocks), dim3(256), 0, st, E2_pair, p.npair,
                      tpart);

@@ -191,6 +191,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     __syncthreads();
     if (it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
+    if (ne == 0) continue;  // an item emptied by a pair mask
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
     const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
@@ -285,14 +286,15 @@ size_t split_lds_bytes(int pw) { return (size_t)2 * kTile * (2 * pw + 8) * 2; }
 
 template <bool F16, int XB>
 static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds, hipStream_t st,
-                             const char* o, int prec, int pw, const double* gap, double* partial,
+                             const char* o, int prec, int pw, const double* gap,
+                             const Entry* entries, const WorkItem* items, double* partial,
                              int32_t* head) {
   const TileSet& t = p.tiles[prec];
   switch (nch) {
 #define FEF_NCH(N)                                                                                \
   case N:                                                                                         \
     hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(512), lds, st, p.d_frag,       \
-                       p.d_pair, p.d_slot_pair, t.d_xblocks, t.d_entries, t.d_items,              \
+                       p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,                      \
                        (int32_t)t.nitems, head, o, prec, pw, gap, partial);                       \
     break;
     FEF_NCH(1) FEF_NCH(2) FEF_NCH(3) FEF_NCH(4) FEF_NCH(5) FEF_NCH(6) FEF_NCH(7) FEF_NCH(8)
@@ -301,8 +303,8 @@ static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds
 }
 
 hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
-                              fef_prec prec, double* partial, int32_t* head, int grid,
-                              hipStream_t st) {
+                              fef_prec prec, const Entry* entries, const WorkItem* items,
+                              double* partial, int32_t* head, int grid, hipStream_t st) {
   const char* o = static_cast<const char*>(ops);
   const int pw = p.geom[prec].pw, nch = p.geom[prec].kpad / 32;
   const int xb = p.tiles[prec].xb;
@@ -310,11 +312,11 @@ hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double
   const size_t lds = split_lds_bytes(pw);
   const dim3 g(grid);
   if (prec == FEF_FP16X2) {
-    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
-    else launch_split_nch<true, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_nch<true, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else if (prec == FEF_BF16X2) {
-    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
-    else launch_split_nch<false, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, partial, head);
+    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_nch<false, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else {
     return hipErrorInvalidValue;
   }

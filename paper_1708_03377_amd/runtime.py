@@ -44,7 +44,8 @@ class Context:
         self.ops: Dict[int, "torch.Tensor"] = {}
         ws = max([q(F.Q_HALF_WS_BYTES, p) for p in F.PREC.values()] +
                  [q(F.Q_PAIR_WS_BYTES, p) for p in F.PREC.values()] +
-                 [q(F.Q_FIELD_WS_BYTES), q(F.Q_SCF_WS_BYTES)])
+                 [q(F.Q_MASKED_WS_BYTES, p) for p in F.PREC.values()] +
+                 [q(F.Q_FIELD_WS_BYTES), q(F.Q_SCF_WS_BYTES), q(F.Q_SURR_WS_BYTES)])
         self.ws = torch.empty(ws, dtype=torch.uint8, device=self.device)
         self.sizes = {"bov": q(F.Q_BOV_ELEMS), "w": q(F.Q_W_ELEMS), "c": q(F.Q_C_ELEMS)}
         self._q = q
@@ -111,3 +112,52 @@ class Context:
         """Half transform + pair energies on the current orbitals."""
         self.half_transform(prec)
         return self.pair_energies(prec)
+
+    # ---- surrogate ---------------------------------------------------------
+    def pair_energies_masked(self, prec: int, select):
+        """Exact pair energies of the selected pairs; the others keep the
+        values already in E2_pair."""
+        F.fef_pair_energies_masked(self.plan, self.ops_for(prec), self.eps, prec, select,
+                                   self.E2_pair, self.E2_total, self.flags, self.ws,
+                                   self.stream())
+        return self.E2_pair[:self.npair], self.E2_total
+
+    def coupling_modes(self):
+        if getattr(self, "_Q", None) is None:
+            self._Q = self.torch.zeros(4 * int(self.system.naux_class[0]),
+                                       dtype=self.torch.float64, device=self.device)
+            F.fef_coupling_modes(self.plan, self.G, self._Q, self.ws, self.stream())
+        return self._Q
+
+    def invariants(self):
+        """U [nfrag][8] from the current density D (after scf)."""
+        U = self.torch.empty(max(self.system.nfrag, 1) * 8, dtype=self.torch.float64,
+                             device=self.device)
+        F.fef_fragment_invariants(self.plan, self.B, self.G, self.D, self.coupling_modes(), U,
+                                  self.ws, self.stream())
+        return U
+
+    def pair_features(self, U, idx=None, with_targets=False):
+        """Raw features X [n][17] (and targets E2 R^2) of the pairs idx
+        (a device int32 tensor) or of every pair."""
+        n = self.npair if idx is None else int(idx.numel())
+        X = self.torch.empty(max(n, 1) * 17, dtype=self.torch.float32, device=self.device)
+        T = self.torch.empty(max(n, 1), dtype=self.torch.float32, device=self.device) \
+            if with_targets else None
+        F.fef_pair_features(self.plan, U, self.E2_pair if with_targets else None, idx, n, X, T,
+                            self.stream())
+        return (X[:n * 17].view(n, 17), T[:n] if with_targets else None)
+
+    def surrogate_energies(self, ens, U, r_exact_bohr: float, threshold: float,
+                           prec: int = F.PREC["bf16x2"]):
+        """Surrogate pass on the current orbitals: the ensemble predicts the
+        pairs it agrees on, the exact kernel (mode ``prec``) evaluates the
+        rest.  Returns (E2_pair, E2_total, select)."""
+        if getattr(self, "_select", None) is None:
+            self._select = self.torch.zeros(max(self.npair, 1), dtype=self.torch.int32,
+                                            device=self.device)
+        F.fef_surrogate_select(self.plan, U, ens.nmember, ens.stats, ens.W, r_exact_bohr,
+                               threshold, self.E2_pair, self._select, self.stream())
+        self.half_transform(prec)
+        E2, tot = self.pair_energies_masked(prec, self._select)
+        return E2, tot, self._select[:self.npair]

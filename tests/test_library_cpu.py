@@ -81,3 +81,40 @@ def test_missing_library_fails_loudly(tmp_path):
     from paper_1708_03377_amd import _fef
     with pytest.raises(RuntimeError, match="missing"):
         _fef.load_library(str(tmp_path / "libfef.so"))
+
+
+def test_surrogate_entry_points_reject_bad_arguments():
+    F, lib = _lib()
+    out = ctypes.c_int64()
+    assert lib.fef_pair_energies_masked(None, None, None, 0, None, None, None, None, None, 0,
+                                        None) == F.FEF_E_ARG
+    assert lib.fef_coupling_modes(None, None, None, None, 0, None) == F.FEF_E_ARG
+    assert lib.fef_fragment_invariants(None, None, None, None, None, None, None, 0,
+                                       None) == F.FEF_E_ARG
+    assert lib.fef_pair_features(None, None, None, None, 0, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_column_stats(10, 0, 0, None, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_mlp_pack(0, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_mlp_forward(0, 1, None, None, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_mlp_forward(65, 1, None, None, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_mlp_train_ws_bytes(0, 10, ctypes.byref(out)) == F.FEF_E_ARG
+    assert lib.fef_mlp_train_ws_bytes(5, 64, ctypes.byref(out)) == F.FEF_OK
+    # 2 blocks of 32 rows per member: partial gradients + partial losses
+    assert out.value >= 5 * 2 * F.MLP_STRIDE * 4 + 5 * 2 * 4
+    assert lib.fef_mlp_train_step(5, None, None, None, 8, None, None, None, None, None, 1,
+                                  ctypes.c_float(1e-3), None, None, None, 0,
+                                  None) == F.FEF_E_ARG
+    assert lib.fef_surrogate_select(None, None, 5, None, None, 0.0, 0.0, None, None,
+                                    None) == F.FEF_E_ARG
+
+
+def test_mlp_layout_constants_match_header():
+    import fefgen
+    F, _ = _lib()
+    txt = open(os.path.join(ROOT, "include", "fef.h")).read()
+    for name, val in (("FEF_MLP_NIN", F.MLP_NIN), ("FEF_MLP_NHID", F.MLP_NHID),
+                      ("FEF_MLP_NPARAM", F.MLP_NPARAM), ("FEF_MLP_STRIDE", F.MLP_STRIDE),
+                      ("FEF_MLP_NSTATS", F.MLP_NSTATS)):
+        assert re.search(rf"#define {name} {val}\b", txt), name
+    assert fefgen.MLP_STRIDE == F.MLP_STRIDE
+    sizes = [17 * 128, 128, 128 * 128, 128, 128, 1]
+    assert sum(sizes) == F.MLP_NPARAM
