@@ -258,6 +258,15 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     else if (n <= 48) p->eig_mid.push_back(f);
     else { p->eig_large.push_back(f); p->eig_large_max_nbf = std::max(p->eig_large_max_nbf, n); }
   }
+  {  // group the n <= 32 fragments by register-kernel size class (8, 16, 24, 32)
+    auto cls_of = [&](int f) { const int n = p->frag[f].nbf; return n <= 8 ? 0 : n <= 16 ? 1 : n <= 24 ? 2 : 3; };
+    std::stable_sort(p->eig_small.begin(), p->eig_small.end(),
+                     [&](int a, int b) { return cls_of(a) < cls_of(b); });
+    int32_t cnt[4] = {0, 0, 0, 0};
+    for (int f : p->eig_small) ++cnt[cls_of(f)];
+    p->eig_w_off[0] = 0;
+    for (int c = 0; c < 4; ++c) p->eig_w_off[c + 1] = p->eig_w_off[c] + cnt[c];
+  }
 
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = upload(&p->d_frag, p->frag);

@@ -100,6 +100,7 @@ struct fef_plan_s {
   fef::OpsGeom geom[FEF_NPREC];
   // eigen-solver groups: fragments by size class
   std::vector<int32_t> eig_small, eig_mid, eig_large;
+  int32_t eig_w_off[5] = {0, 0, 0, 0, 0};  // eig_small ranges with n <= 8, 16, 24, 32
   int32_t eig_large_max_nbf = 0;
   int64_t ht_ntasks = 0;
   std::vector<int32_t> ht_fused, ht_generic;  // half-transform paths per fragment

@@ -298,6 +298,234 @@ __global__ __launch_bounds__(NT) void eigh_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident Jacobi for n <= 32: two matrices per wave, one per half
+// (32 lanes).  Matrix size M (even, >= n; indices n..M-1 are decoupled zero
+// rows/columns).  Lane t of a half holds row t of A and row t of V (AO row t)
+// in registers, columns in "slot" order.  In every round the pairs are the
+// slots (2k, 2k+1): each lane pair computes its rotation, the rotations are
+// broadcast through LDS for the column updates (A <- A J, V <- V J, register
+// pairs), and the row update (A <- J^T A) swaps rows between the two lanes of
+// a pair with DPP.  Then the slots are relabelled by the circle-method
+// permutation pi (a fixed slot stays, the others move one place round a
+// circle), applied to A's rows (ds_bpermute straight into the permuted
+// registers) and to the columns of A and V.  Over the M - 1 rounds of a
+// sweep every pair of indices meets once and pi^(M-1) is the identity, so at
+// the start of every sweep slot j holds index j again.  Same rotation
+// formula, warm start (A = C^T F C, V = C) and stopping rule as above.
+template <int M>
+struct SlotPerm {
+  // pi(s): the slot the contents of slot s move to after a round
+  static constexpr int pi(int s) {
+    return s == 0 ? 0
+         : s == 1 ? (M > 2 ? 2 : 1)
+         : (s % 2 == 0) ? (s / 2 + 1 <= M / 2 - 1 ? s + 2 : M - 1)
+                        : (s / 2 >= 2 ? s - 2 : 1);
+  }
+  static constexpr int inv(int j) {
+    int r = 0;
+    for (int s = 0; s < M; ++s)
+      if (pi(s) == j) r = s;
+    return r;
+  }
+};
+
+__device__ inline double dpp_swap_pair(double x) {  // value of lane ^ 1
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double bperm_d(int byte_addr, double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(byte_addr, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int M>
+__global__ __launch_bounds__(64) void eigh_wave_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list, int32_t count,
+    const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
+    double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
+    int32_t* __restrict__ flags) {
+  static_assert(M % 2 == 0 && M >= 2 && M <= 32, "half-wave matrix size");
+  constexpr int LD = M + 1;
+  __shared__ double S1[2][M * LD];
+  __shared__ double S2[2][M * LD];
+  __shared__ double csb[2][M];      // (c, s) of the M/2 pairs
+  __shared__ double lam[2][M];
+  __shared__ int32_t rk[2][M];
+  __shared__ int32_t occ[2][M];
+  const int lane = threadIdx.x, h = lane >> 5, t = lane & 31;
+  const int mi = blockIdx.x * 2 + h;
+  const bool active = mi < count;
+  const int f = active ? list[mi] : 0;
+  const int n = active ? frag[f].nbf : 0;
+  const int nocc = active ? frag[f].nocc : 0;
+  const int64_t oc = active ? frag[f].off_C : 0;
+  double* s1 = S1[h];
+  double* s2 = S2[h];
+  // ---- warm start: S1 = C, S2 = F_sym C, then A = C^T (F C)
+  for (int e = t; e < M * M; e += 32) {
+    const int i = e / M, j = e - (e / M) * M;
+    s1[i * LD + j] = (i < n && j < n) ? C[oc + i * n + j] : 0.0;
+  }
+  __syncthreads();
+  if (t < M) {
+    double frow[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+      frow[k] = (t < n && k < n) ? 0.5 * (F[oc + t * n + k] + F[oc + k * n + t]) : 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) acc = fma(frow[k], s1[k * LD + j], acc);
+      s2[t * LD + j] = acc;
+    }
+  }
+  __syncthreads();
+  double a[M], v[M];
+  if (t < M) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) acc = fma(s1[i * LD + t], s2[i * LD + j], acc);
+      a[j] = acc;
+      v[j] = s1[t * LD + j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) { a[j] = 0.0; v[j] = 0.0; }
+  }
+  __syncthreads();
+  if (t < M)
+#pragma unroll
+    for (int j = 0; j < M; ++j) s2[t * LD + j] = a[j];
+  __syncthreads();
+  if (t < M)
+#pragma unroll
+    for (int j = 0; j < M; ++j) a[j] = 0.5 * (s2[t * LD + j] + s2[j * LD + t]);
+  // lane t of this half receives the row of lane pi^-1(t) after each round
+  int src = t;
+#pragma unroll
+  for (int s = 0; s < M; ++s)
+    if (SlotPerm<M>::pi(s) == t) src = s;
+  const int src_addr = 4 * (h * 32 + (t < M ? src : t));
+  const bool odd = (t & 1) != 0;
+
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const double q = a[j] * a[j];
+      if (j == t) dia = q; else off += q;
+    }
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 32);
+      dia += __shfl_xor(dia, o, 32);
+    }
+    const bool done = off <= 1e-28 * dia || !(off == off);
+    if (__all(done)) break;
+    for (int r = 0; r < M - 1; ++r) {
+      // this lane's pair (slots 2k, 2k+1): diagonal and off-diagonal entries
+      double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < M / 2; ++k)
+        if (2 * k == (t & ~1)) { x0 = a[2 * k]; x1 = a[2 * k + 1]; }
+      const double d = odd ? x1 : x0, o = odd ? x0 : x1;
+      const double dp = dpp_swap_pair(d), op = dpp_swap_pair(o);
+      const double app = odd ? dp : d, aqq = odd ? d : dp, apq = odd ? op : o;
+      double c, s;
+      jacobi_rotation(app, aqq, apq, c, s);
+      if (done) { c = 1.0; s = 0.0; }
+      if (!odd && t < M) { csb[h][t] = c; csb[h][t + 1] = s; }
+      __syncthreads();
+      // columns of A and V
+#pragma unroll
+      for (int k = 0; k < M / 2; ++k) {
+        const double ck = csb[h][2 * k], sk = csb[h][2 * k + 1];
+        const double ap = a[2 * k], aq = a[2 * k + 1];
+        a[2 * k] = ck * ap - sk * aq;
+        a[2 * k + 1] = sk * ap + ck * aq;
+        const double vp = v[2 * k], vq = v[2 * k + 1];
+        v[2 * k] = ck * vp - sk * vq;
+        v[2 * k + 1] = sk * vp + ck * vq;
+      }
+      // rows of A with the partner lane
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const double pj = dpp_swap_pair(a[j]);
+        a[j] = odd ? s * pj + c * a[j] : c * a[j] - s * pj;
+      }
+      // relabel the slots
+      double na[M], nv[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        na[j] = bperm_d(src_addr, a[SlotPerm<M>::inv(j)]);
+        nv[j] = v[SlotPerm<M>::inv(j)];
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j) { a[j] = na[j]; v[j] = nv[j]; }
+    }
+  }
+
+  // ---- eigenvalues (slot j = index j), ranks, outputs
+  double lt = 0.0;
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+    if (j == t) lt = a[j];
+  if (t < M) lam[h][t] = lt;
+  __syncthreads();
+  if (t < n) {
+    int r0 = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = lam[h][j];
+      r0 += (lj < lt) || (lj == lt && j < t);
+    }
+    rk[h][t] = r0;
+    if (r0 < nocc) occ[h][r0] = t;
+    eps[frag[f].off_eps + r0] = lt;
+  }
+  __syncthreads();
+  if (t < n) {
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+      if (j < n) C[oc + t * n + rk[h][j]] = v[j];
+#pragma unroll
+    for (int j = 0; j < M; ++j) s1[t * LD + j] = v[j];
+  }
+  __syncthreads();
+  double dmax = 0.0;
+  if (t < n) {
+    for (int j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int k = 0; k < nocc; ++k) {
+        const int sl = occ[h][k];
+        acc = fma(s1[t * LD + sl], s1[j * LD + sl], acc);
+      }
+      Dnew[oc + t * n + j] = acc;
+      dmax = fmax(dmax, fabs(acc - Dold[oc + t * n + j]));
+    }
+  }
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 32));
+  if (active && t == 0) {
+    atomic_max_nonneg(dD_max, dmax);
+    if (nocc > 0 && nocc < n) {
+      double lh = 0.0, ll = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (rk[h][j] == nocc - 1) lh = lam[h][j];
+        if (rk[h][j] == nocc) ll = lam[h][j];
+      }
+      if (!(ll > lh)) atomicOr(flags, FEF_FLAG_GAP);
+    }
+  }
+}
+
 // rotation table (c, s, p, q per pair) + ranks + sorted eigenvalues
 static size_t eig_scratch_bytes(int n) {
   const int half = (n + 1) / 2;
@@ -308,12 +536,25 @@ static size_t eig_scratch_bytes(int n) {
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold, double* C,
                        double* eps, double* Dnew, double* dD_max, int32_t* flags,
                        double* ws_eig, hipStream_t st) {
-  if (!p.eig_small.empty()) {
-    const int nmax = 32;
-    const size_t lds = 3 * (size_t)nmax * (nmax + 1) * sizeof(double) + eig_scratch_bytes(nmax);
-    hipLaunchKernelGGL((eigh_kernel<64, 32>), dim3((unsigned)p.eig_small.size()), dim3(64), lds,
-                       st, p.d_frag, p.d_eig_small, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig,
-                       nmax);
+  // n <= 32: register-resident kernels, one size class per launch
+  {
+    const int sizes[4] = {8, 16, 24, 32};
+    for (int c = 0; c < 4; ++c) {
+      const int32_t b = p.eig_w_off[c], cnt = p.eig_w_off[c + 1] - b;
+      if (cnt == 0) continue;
+      const dim3 grid((unsigned)((cnt + 1) / 2));
+      const int32_t* lst = p.d_eig_small + b;
+#define FEF_EIGW(MM)                                                                          \
+  hipLaunchKernelGGL((eigh_wave_kernel<MM>), grid, dim3(64), 0, st, p.d_frag, lst, cnt, F,    \
+                     Dold, C, eps, Dnew, dD_max, flags)
+      switch (sizes[c]) {
+        case 8: FEF_EIGW(8); break;
+        case 16: FEF_EIGW(16); break;
+        case 24: FEF_EIGW(24); break;
+        default: FEF_EIGW(32); break;
+      }
+#undef FEF_EIGW
+    }
   }
   if (!p.eig_mid.empty()) {
     const int nmax = 48;
