@@ -31,28 +31,43 @@ __global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict
 
 __global__ void zero_scalar_kernel(double* p) { *p = 0.0; }
 
-// d^x_Q: one wave per Q, four Q per block.
+// d^x_Q: each wave reduces four Q against one pass over D, sixteen Q per
+// block (fixed summation order: lane-strided partial sums, then the wave).
+constexpr int kMomQ = 4;
 __global__ __launch_bounds__(256) void moments_kernel(const FragInfo* __restrict__ frag,
                                                       const double* __restrict__ B,
                                                       const double* __restrict__ D,
                                                       double* __restrict__ dmom) {
   const FragInfo fi = frag[blockIdx.x];
-  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (q >= fi.naux) return;
+  const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQ;
+  if (q0 >= fi.naux) return;
   const int lane = threadIdx.x & 63;
+  const int nq = min(kMomQ, fi.naux - q0);
   const int nn = fi.nbf * fi.nbf;
-  const double* b = B + fi.off_B + (int64_t)q * nn;
+  const double* b = B + fi.off_B + (int64_t)q0 * nn;
   const double* d = D + fi.off_C;
-  double acc = 0.0;
-  for (int e = lane; e < nn; e += 64) acc = fma(b[e], d[e], acc);
-  acc = wave_sum(acc);
-  if (lane == 0) dmom[fi.off_aux + q] = acc;
+  double acc[kMomQ] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = lane; e < nn; e += 64) {
+    const double dv = d[e];
+#pragma unroll
+    for (int k = 0; k < kMomQ; ++k)
+      if (k < nq) acc[k] = fma(b[(int64_t)k * nn + e], dv, acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kMomQ; ++k) {
+    const double t = wave_sum(acc[k]);
+    if (lane == 0 && k < nq) dmom[fi.off_aux + q0 + k] = t;
+  }
 }
 
 // phi^x.  The neighbour moments are first summed per class,
 // e_c = sum_{y in nbr(x), c(y) = c} s_xy d^y, then phi^x = sum_c G_{c(x) c} e_c
-// with G_{c,0} stored and G_{0,c} = G_{c,0}^T.  Wave w takes the neighbours
-// w, w + 4, ... of x in list order and keeps class-0 sums in registers
+// with G_{c,0} stored and G_{0,c} = G_{c,0}^T.  Wave w takes the chunks of 64
+// neighbours w, w + 4, ... in list order: each lane first loads one
+// neighbour's index, coupling and table entries (one memory round trip for 64
+// neighbours), then the wave walks the chunk in order, taking each
+// neighbour's entries from its lane, so the moment loads of successive
+// neighbours are independent and overlap.  Class-0 sums stay in registers
 // (rows lane, lane + 64 of the P0 vector); the four wave partials are added
 // in wave order, so the result is deterministic.
 __global__ __launch_bounds__(256) void field_kernel(
@@ -70,18 +85,37 @@ __global__ __launch_bounds__(256) void field_kernel(
   double* mine = part + wave * etot;
   const int beg = nbr_ptr[x], end = nbr_ptr[x + 1];
   double e0 = 0.0, e1 = 0.0;
-#pragma unroll 4
-  for (int k = beg + wave; k < end; k += 4) {
-    const int y = nbr_idx[k];
-    const double s = nbr_s[k];
-    const int cy = frag[y].cls;
-    const double* dy = dmom + frag[y].off_aux;
-    if (cy == 0) {
-      if (lane < P0) e0 = fma(s, dy[lane], e0);
-      if (lane + 64 < P0) e1 = fma(s, dy[lane + 64], e1);
-    } else {
-      const int base = naux_cls_off[cy], pc = frag[y].naux;
-      for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
+  for (int c0 = beg + 64 * wave; c0 < end; c0 += 256) {
+    const int k = c0 + lane;
+    int y_cls = 0, y_naux = 0;
+    int64_t y_off = 0;
+    double y_s = 0.0;
+    if (k < end) {
+      const int y = nbr_idx[k];
+      y_s = nbr_s[k];
+      y_cls = frag[y].cls;
+      y_naux = frag[y].naux;
+      y_off = frag[y].off_aux;
+    }
+    const int cnt = min(64, end - c0);
+#pragma unroll 8
+    for (int j = 0; j < cnt; ++j) {
+      const int cy = __builtin_amdgcn_readlane(y_cls, j);
+      const int lo = __builtin_amdgcn_readlane((int)y_off, j);
+      const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
+      const int64_t off = ((int64_t)hi << 32) | (uint32_t)lo;
+      const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
+                           0xffffffffLL;
+      const long long sh = __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
+      const double s = __longlong_as_double((sh << 32) | sb);
+      const double* dy = dmom + off;
+      if (cy == 0) {
+        if (lane < P0) e0 = fma(s, dy[lane], e0);
+        if (lane + 64 < P0) e1 = fma(s, dy[lane + 64], e1);
+      } else {
+        const int base = naux_cls_off[cy], pc = __builtin_amdgcn_readlane(y_naux, j);
+        for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
+      }
     }
   }
   if (lane < P0) mine[lane] += e0;
@@ -97,7 +131,11 @@ __global__ __launch_bounds__(256) void field_kernel(
     for (int c = 0; c < nclass; ++c) {
       const int pc = naux_cls_off[c + 1] - naux_cls_off[c];
       const double* ec = part + naux_cls_off[c];
-      if (c == 0) {
+      if (c == 0 && cx == 0) {
+        // G_{0,0} is symmetric: read it by columns, so that consecutive
+        // threads (rows p) load consecutive addresses
+        for (int q = 0; q < pc; ++q) acc = fma(G[(int64_t)q * P0 + p], ec[q], acc);
+      } else if (c == 0) {
         const double* g = G + off_G[cx];  // G_{cx,0}: [P_cx][P0]
         for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)p * P0 + q], ec[q], acc);
       } else if (cx == 0) {
@@ -109,7 +147,9 @@ __global__ __launch_bounds__(256) void field_kernel(
   }
 }
 
-// out^x[mu nu] = (F0 + h~)[mu nu] + 2 sum_P B^x[P][mu nu] phi^x_P.
+// out^x[mu nu] = (F0 + h~)[mu nu] + 2 sum_P B^x[P][mu nu] phi^x_P.  Each
+// thread takes two neighbouring elements (16-byte loads when nbf^2 and the
+// fragment's B offset are even).
 __global__ __launch_bounds__(256) void jbuild_kernel(const FragInfo* __restrict__ frag,
                                                      const double* __restrict__ B,
                                                      const double* __restrict__ phi,
@@ -118,16 +158,33 @@ __global__ __launch_bounds__(256) void jbuild_kernel(const FragInfo* __restrict_
                                                      double* __restrict__ out) {
   const FragInfo fi = frag[blockIdx.x];
   const int nn = fi.nbf * fi.nbf;
-  const int e = blockIdx.y * blockDim.x + threadIdx.x;
+  const int e = 2 * (blockIdx.y * blockDim.x + threadIdx.x);
   if (e >= nn) return;
   const double* b = B + fi.off_B + e;
   const double* ph = phi + fi.off_aux;
-  double acc = 0.0;
-  for (int P = 0; P < fi.naux; ++P) acc = fma(b[(int64_t)P * nn], ph[P], acc);
-  double v = 2.0 * acc;
-  if (F0) v += F0[fi.off_C + e];
-  if (htilde) v += htilde[fi.off_C + e];
-  out[fi.off_C + e] = v;
+  double a0 = 0.0, a1 = 0.0;
+  if ((nn & 1) == 0 && (fi.off_B & 1) == 0) {
+#pragma unroll 8
+    for (int P = 0; P < fi.naux; ++P) {
+      const double2 v = *reinterpret_cast<const double2*>(b + (int64_t)P * nn);
+      const double f = ph[P];
+      a0 = fma(v.x, f, a0);
+      a1 = fma(v.y, f, a1);
+    }
+  } else {
+    const bool two = e + 1 < nn;
+    for (int P = 0; P < fi.naux; ++P) {
+      const double f = ph[P];
+      a0 = fma(b[(int64_t)P * nn], f, a0);
+      if (two) a1 = fma(b[(int64_t)P * nn + 1], f, a1);
+    }
+  }
+  const int64_t o = fi.off_C + e;
+  double v0 = 2.0 * a0, v1 = 2.0 * a1;
+  if (F0) { v0 += F0[o]; if (e + 1 < nn) v1 += F0[o + 1]; }
+  if (htilde) { v0 += htilde[o]; if (e + 1 < nn) v1 += htilde[o + 1]; }
+  out[o] = v0;
+  if (e + 1 < nn) out[o + 1] = v1;
 }
 
 hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* dD_max,
@@ -142,22 +199,22 @@ hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, doubl
 
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st) {
-  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 3) / 4), dim3(256), 0, st,
-                     p.d_frag, B, D, dmom);
+  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)),
+                     dim3(256), 0, st, p.d_frag, B, D, dmom);
   return hipGetLastError();
 }
 
 hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G, const double* D,
                         const double* F0, const double* htilde, double* out, double* ws_d,
                         double* ws_phi, hipStream_t st) {
-  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 3) / 4), dim3(256), 0, st,
-                     p.d_frag, B, D, ws_d);
+  hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)),
+                     dim3(256), 0, st, p.d_frag, B, D, ws_d);
   const int etot = p.naux_cls_off.back();
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                      p.d_naux_cls_off, ws_d, ws_phi);
   const int nnmax = p.max_nbf * p.max_nbf;
-  hipLaunchKernelGGL(jbuild_kernel, dim3(p.nfrag, (nnmax + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(jbuild_kernel, dim3(p.nfrag, (nnmax + 511) / 512), dim3(256), 0, st,
                      p.d_frag, B, ws_phi, F0, htilde, out);
   return hipGetLastError();
 }

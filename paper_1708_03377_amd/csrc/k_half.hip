@@ -22,11 +22,10 @@ namespace fef {
 //    then X = C_occ^T B_P and B_ov = X C_vir are formed from LDS and B_ov is
 //    written densely.  Thousands of workgroups keep HBM streaming.
 //  ht_pack_small_kernel: one workgroup per fragment: B_ov^x in LDS, W^x =
-//    G^T B_ov^x in registers (up to kMaxW outputs per thread), and both
+//    G^T B_ov^x on FP64 MFMA (accumulators stay in registers), and both
 //    pair-kernel operands of mode PREC written directly (FP16 scales from
 //    block-wide maxima).
 constexpr int kSmallP = 80, kSliceGroup = 8;
-constexpr int kMaxW = (kSmallP * kTile + 255) / 256;
 
 __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __restrict__ frag,
                                                           const int32_t* __restrict__ list,
@@ -78,36 +77,59 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const double* __restrict__ bov, const double* __restrict__ G,
     const int64_t* __restrict__ off_G, int P0, int kpad, int pw, double* __restrict__ w_out,
     char* __restrict__ ops) {
-  __shared__ double Bs[kSmallP * kTile];
+  __shared__ double Bs[kSmallP * kTile];  // [P][96], zero past ov and past P (to a multiple of 4)
   __shared__ double red[4];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int ov = fi.ov, P = fi.naux;
-  for (int e = threadIdx.x; e < P * ov; e += 256) Bs[e] = bov[fi.off_bov + e];
+  const int P4 = (P + 3) & ~3;
+  for (int e = threadIdx.x; e < P4 * kTile; e += 256) {
+    const int pp = e / kTile, ia = e - (e / kTile) * kTile;
+    Bs[e] = (pp < P && ia < ov) ? bov[fi.off_bov + (int64_t)pp * ov + ia] : 0.0;
+  }
   __syncthreads();
-  // W = G_{c,0}^T B_ov into registers
+  // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia tile),
+  // tile t = wave + 4 k; A = G^T read from the (L2-resident) coupling, B from LDS
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
   const double* g = G + off_G[fi.cls];  // [P][P0]
-  double wv[kMaxW];
+  const int QT = (P0 + 15) >> 4, NT = QT * (kTile / 16);
+  constexpr int kTilesPerWave = (5 * (kTile / 16) + 3) / 4;
+  d4 acc[kTilesPerWave];
+#pragma unroll
+  for (int k = 0; k < kTilesPerWave; ++k) acc[k] = d4{0, 0, 0, 0};
+  for (int ks = 0; ks < P4 / 4; ++ks) {
+    const int pp = 4 * ks + lk;
+#pragma unroll
+    for (int k = 0; k < kTilesPerWave; ++k) {
+      const int t = wave + 4 * k;
+      if (t < NT) {
+        const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
+        const int q = 16 * qt + li;
+        const double av = (pp < P && q < P0) ? g[(int64_t)pp * P0 + q] : 0.0;
+        const double bv = Bs[pp * kTile + 16 * it + li];
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
+      }
+    }
+  }
+  // element (r) of tile k: q = 16 qt + lk + 4 r, ia = 16 it + li
   double wmax = 0.0, bmax = 0.0;
 #pragma unroll
-  for (int u = 0; u < kMaxW; ++u) {
-    const int e = threadIdx.x + 256 * u;
-    double acc = 0.0;
-    if (e < P0 * ov) {
-      const int q = e / ov, ia = e - (e / ov) * ov;
-      for (int pp = 0; pp < P; ++pp) acc = fma(g[(int64_t)pp * P0 + q], Bs[pp * ov + ia], acc);
-    }
-    wv[u] = acc;
-    wmax = fmax(wmax, fabs(acc));
-  }
-  for (int e = threadIdx.x; e < P * ov; e += 256) bmax = fmax(bmax, fabs(Bs[e]));
-  if (w_out) {
+  for (int k = 0; k < kTilesPerWave; ++k) {
+    const int t = wave + 4 * k;
+    if (t < NT) {
+      const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
 #pragma unroll
-    for (int u = 0; u < kMaxW; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < P0 * ov) w_out[fi.off_w + e] = wv[u];
+      for (int r = 0; r < 4; ++r) {
+        const int q = 16 * qt + lk + 4 * r, ia = 16 * it + li;
+        if (q < P0 && ia < ov) {
+          wmax = fmax(wmax, fabs(acc[k][r]));
+          if (w_out) w_out[fi.off_w + (int64_t)q * ov + ia] = acc[k][r];
+        }
+      }
     }
   }
+  for (int e = threadIdx.x; e < P * kTile; e += 256) bmax = fmax(bmax, fabs(Bs[e]));
   const bool right = fi.off_R[PREC] >= 0;
   if (PREC == FEF_F64 || PREC == FEF_F32) {
     typedef typename std::conditional<PREC == FEF_F64, double, float>::type T;
@@ -115,11 +137,15 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     T* R = right ? reinterpret_cast<T*>(ops + fi.off_R[PREC]) : nullptr;
     // [kpad][ld]: values, then zeros in the padding
 #pragma unroll
-    for (int u = 0; u < kMaxW; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < P0 * ov) {
-        const int q = e / ov, ia = e - (e / ov) * ov;
-        L[(int64_t)q * fi.ld + ia] = (T)wv[u];
+    for (int k = 0; k < kTilesPerWave; ++k) {
+      const int t = wave + 4 * k;
+      if (t < NT) {
+        const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * qt + lk + 4 * r, ia = 16 * it + li;
+          if (q < P0 && ia < ov) L[(int64_t)q * fi.ld + ia] = (T)acc[k][r];
+        }
       }
     }
     for (int e = threadIdx.x; e < kpad * kTile; e += 256) {
@@ -128,7 +154,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
         L[(int64_t)k * fi.ld + m] = (T)0;
         if (R) R[(int64_t)k * fi.ld + m] = (T)0;
       } else if (R) {
-        R[(int64_t)k * fi.ld + m] = (T)Bs[k * ov + m];
+        R[(int64_t)k * fi.ld + m] = (T)Bs[k * kTile + m];
       }
     }
   } else {
@@ -146,26 +172,31 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
     uint16_t* R = right ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
 #pragma unroll
-    for (int u = 0; u < kMaxW; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      if (e < P0 * ov) {
-        const int q = e / ov, ia = e - (e / ov) * ov;
-        uint16_t hi, lo;
-        split2<kF16>(wv[u] * sL, hi, lo);
-        L[ia * xs + q] = hi;
-        L[ia * xs + pw + q] = lo;
+    for (int k = 0; k < kTilesPerWave; ++k) {
+      const int t = wave + 4 * k;
+      if (t < NT) {
+        const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 16 * qt + lk + 4 * r, ia = 16 * it + li;
+          if (q < P0 && ia < ov) {
+            uint16_t hi, lo;
+            split2<kF16>(acc[k][r] * sL, hi, lo);
+            L[ia * xs + q] = hi;
+            L[ia * xs + pw + q] = lo;
+          }
+        }
       }
     }
     if (R)
       for (int e = threadIdx.x; e < P0 * ov; e += 256) {
         const int q = e / ov, ia = e - (e / ov) * ov;
         uint16_t hi, lo;
-        split2<kF16>(Bs[q * ov + ia] * sR, hi, lo);
+        split2<kF16>(Bs[q * kTile + ia] * sR, hi, lo);
         R[ia * xs + q] = hi;
         R[ia * xs + pw + q] = lo;
       }
     // zeros: rows past ov, and the columns past P0 in each plane plus the tail
-    const int pad = pw - P0;
     for (int e = threadIdx.x; e < kTile * xs; e += 256) {
       const int m = e / xs, k = e - (e / xs) * xs;
       const bool z = m >= ov || (k >= P0 && k < pw) || k >= pw + P0;
@@ -174,7 +205,6 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
         if (R) R[e] = 0;
       }
     }
-    (void)pad;
   }
 }
 
