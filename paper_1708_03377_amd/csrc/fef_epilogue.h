@@ -74,35 +74,4 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
   return sum;
 }
 
-// Split-precision epilogue with FP64 weights: the FP32 accumulator is
-// widened, the reciprocal of the FP64 denominator comes from the hardware
-// approximation refined by two Newton steps, products and sums in FP64.
-template <int TI, int TJ>
-__device__ inline double weighted_tiles_f64w(const f4 (&acc)[TI][TJ], const double* gx,
-                                             const double* gy, int lane) {
-  const int li = lane & 15, lk = lane >> 4;
-  double dx[TI][4], dy[TJ];
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + 4 * lk + r];
-#pragma unroll
-  for (int j = 0; j < TJ; ++j) dy[j] = gy[16 * j + li];
-  double sum = 0.0;
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int j = 0; j < TJ; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double d = dx[i][r] + dy[j];
-        double w = __builtin_amdgcn_rcp(d);
-        w = fma(w, fma(-d, w, 1.0), w);
-        w = fma(w, fma(-d, w, 1.0), w);
-        const double v = (double)acc[i][j][r];
-        sum = fma(v * v, w, sum);
-      }
-  return sum;
-}
-
 }  // namespace fef

@@ -161,8 +161,8 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
   extern __shared__ char smem[];
   const int xs = 2 * pw + 8;  // row stride (16-bit elements) in HBM and LDS
   uint16_t* Ys = reinterpret_cast<uint16_t*>(smem);  // [2][kTile][xs]
-  __shared__ double Gx[XB * kTile];
-  __shared__ double Gy[2][kTile];
+  __shared__ float Gx[XB * kTile];
+  __shared__ float Gy[2][kTile];
   __shared__ double red[2][NW];
   __shared__ int32_t s_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -213,10 +213,10 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     for (int t = threadIdx.x; t < XB * kTile; t += NT) {
       const int u = t / kTile, m = t - (t / kTile) * kTile;
       const int f = xblocks[xbid].f[u];
-      Gx[t] = f >= 0 ? gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0;
+      Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
     }
     u16x8 pf[NPF];
-    double pg = 0.0;
+    float pg = 0.0f;
 #define FEF_ISSUE(E)                                                                            \
   {                                                                                             \
     const int y_ = entries[E].y, nt_ = entries[E].nt;                                           \
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       const int c_ = threadIdx.x + NT * k_;                                                     \
       if (c_ < tile_ch) pf[k_] = R_[c_];                                                        \
     }                                                                                           \
-    if (threadIdx.x < kTile) pg = gap[frag[y_].off_gap + nt_ * kTile + threadIdx.x];            \
+    if (threadIdx.x < kTile) pg = (float)gap[frag[y_].off_gap + nt_ * kTile + threadIdx.x];     \
   }
 #define FEF_STORE(B)                                                                            \
   {                                                                                             \
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
 #pragma unroll
             for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
         }
-        mine = wave_sum(weighted_tiles_f64w<TI, TJ>(acc, Gx + unit * kTile + r0, Gy[cur] + c0, lane));
+        mine = wave_sum(weighted_tiles_f32<TI, TJ>(acc, Gx + unit * kTile + r0, Gy[cur] + c0, lane));
       }
       if (lane == 0) red[cur][wave] = mine;
       if (e + 1 < end) FEF_STORE(cur ^ 1)

@@ -1,0 +1,95 @@
+"""GPU parity at the full sizes of the benchmark workloads.
+
+* 4000 water fragments (481,815 pairs), the launch configuration bench.py
+  times (autotuned tiles, captured pass of reset + 10 SCF steps + half
+  transform + pair energies): every precision mode's pair energies against
+  the oracle, on sampled pairs the oracle evaluates one by one from the GPU's
+  final orbitals.
+* 1000 water fragments: one full SCF step of every fragment against the
+  oracle (orbital energies and densities), from the generated orbitals.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fefgen
+from oracle import fef as ofef
+
+pytestmark = pytest.mark.gpu
+
+PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
+TOL_PAIR = {"f64": 1e-9, "f32": 1e-6, "bf16x2": 1e-6, "fp16x2": 1e-6}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def water4000():
+    return fefgen.make_system(3)
+
+
+def test_pair_energies_full_size_sampled(torch, water4000):
+    import paper_1708_03377_amd as lib
+    s = water4000
+    ctx = lib.Context(s)
+    rng = np.random.default_rng(2024)
+    sample = np.sort(rng.choice(s.npair, 160, replace=False))
+    # the sample includes the closest and the farthest pairs
+    sample = np.unique(np.concatenate([sample, [int(np.argmax(s.pair_s)),
+                                                int(np.argmin(s.pair_s))]]))
+    totals = {}
+    ref = None
+    for name in ("f64", "f32", "bf16x2", "fp16x2"):
+        p = PREC[name]
+        ctx.reset_orbitals()
+        ctx.scf(s.spec.niter)
+        ctx.autotune(p, reps=1)
+        g = ctx.graph(s.spec.niter, p)
+        ctx.E2_pair.fill_(0.0)
+        ctx.launch(g)
+        torch.cuda.synchronize()
+        E2 = ctx.E2_pair[:ctx.npair].cpu().numpy()
+        totals[name] = float(ctx.E2_total.cpu()[0])
+        assert int(ctx.flags.cpu()[0]) == 0
+        if ref is None:  # oracle on the GPU's final orbitals (identical in every mode)
+            C = ctx.C.cpu().numpy(); eps = ctx.eps.cpu().numpy()
+            ref, _ = ofef.pair_energies(s, C, eps, pairs=(s.pair_x[sample], s.pair_y[sample],
+                                                          s.pair_s[sample]))
+        err = np.max(np.abs(E2[sample] - ref))
+        _say(f"{name}: tiles {lib.fef_plan_get_tiles(ctx.plan, p)} max sampled pair err {err:.3e}"
+             f" total {totals[name]:.12f}")
+        assert err <= TOL_PAIR[name], name
+        # the total is the sum of the pair energies
+        assert totals[name] == pytest.approx(float(np.sum(E2)), rel=1e-12, abs=1e-9)
+        del g
+    for name in ("f32", "fp16x2"):
+        assert abs(totals[name] - totals["f64"]) <= 1e-6, name
+    _say("bf16x2 total error vs f64", totals["bf16x2"] - totals["f64"])
+
+
+def test_scf_step_full_size():
+    import paper_1708_03377_amd as lib
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = fefgen.make_system(1)
+    ctx = lib.Context(s)
+    dmax = float(ctx.scf_step().cpu()[0])
+    C, e, Dl, odmax, ok = ofef.scf_step(s, s.C.copy(), s.eps.copy())
+    assert abs(dmax - odmax) <= 1e-10
+    np.testing.assert_allclose(ctx.eps.cpu().numpy(), e, rtol=0, atol=1e-10)
+    D = ctx.D.cpu().numpy()
+    Dref = np.concatenate([d.ravel() for d in Dl])
+    assert np.max(np.abs(D - Dref)) <= 1e-10
