@@ -120,8 +120,9 @@ typedef enum {
   FEF_Q_NSLOT = 13,         /* pair output tiles (partial-sum slots)     */
   FEF_Q_NENTRIES = 14,      /* streamed y tiles of mode `prec`'s tiling   */
   FEF_Q_MASKED_WS_BYTES = 15, /* workspace of fef_pair_energies_masked   */
-  FEF_Q_SURR_WS_BYTES = 16  /* workspace of fef_coupling_modes and
+  FEF_Q_SURR_WS_BYTES = 16, /* workspace of fef_coupling_modes and
                                fef_fragment_invariants                  */
+  FEF_Q_BPACK_ELEMS = 17    /* doubles in the packed coefficient pool    */
 } fef_query;
 
 /* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES,
@@ -187,6 +188,21 @@ fef_status fef_scf_step(fef_plan plan, const double* B, const double* G,
                         double* eps, double* D, double* dD_max, int32_t* flags,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Packed coefficients: Bp [P_c][nbf (nbf + 1) / 2] per fragment, the upper
+ * triangle (mu <= nu, row-major) of every symmetric slice B^x[P], fragments
+ * concatenated (FEF_Q_BPACK_ELEMS doubles, caller-owned).  B must be
+ * symmetric in (mu, nu), as the header's pool conventions require. */
+fef_status fef_pack_coefficients(fef_plan plan, const double* B, double* Bp, void* stream);
+
+/* fef_scf_step reading the packed coefficients instead of B: the moments
+ * weight off-diagonal entries by 2 and the Coulomb matrix is built on the
+ * upper triangle and mirrored, so each step streams half the bytes.  Same
+ * results as fef_scf_step up to rounding order. */
+fef_status fef_scf_step_packed(fef_plan plan, const double* Bp, const double* G,
+                               const double* F0, const double* htilde, double* C,
+                               double* eps, double* D, double* dD_max, int32_t* flags,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* Captured FEF pass.  All pointers are device pointers that stay valid for
  * the graph's lifetime; the graph bakes them in. */
 typedef struct {
@@ -208,12 +224,15 @@ typedef struct {
   void* ws;               /* workspace, FEF_Q_SCF_WS_BYTES, FEF_Q_HALF_WS_BYTES
                              and FEF_Q_PAIR_WS_BYTES bytes are all needed */
   size_t ws_bytes;
+  double* Bp;             /* nullable: packed coefficient pool; when given,
+                             the pass packs B into it once and runs the
+                             SCF steps with fef_scf_step_packed */
 } fef_pass_args;
 
 typedef struct fef_graph_s* fef_graph;
 
 /* Records one whole FEF pass -- clearing of flags, [reset of C, eps],
- * niter SCF steps
+ * [packing of B], niter SCF steps
  * (fef_scf_step), the half transform and the pair energies in mode `prec`
  * -- into a HIP graph (stream capture on a private default-priority stream;
  * no allocation happens during replay).  Call outside any capture; the plan

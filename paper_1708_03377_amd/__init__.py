@@ -11,7 +11,7 @@ from ._fef import (PREC, FefError, fef_coulomb_field, fef_half_transform,  # noq
                    fef_autotune, fef_pair_energies_masked, fef_coupling_modes,
                    fef_fragment_invariants, fef_pair_features, fef_column_stats, fef_mlp_pack,
                    fef_mlp_forward, fef_mlp_train_step, fef_mlp_train_ws_bytes,
-                   fef_surrogate_select,
+                   fef_surrogate_select, fef_pack_coefficients, fef_scf_step_packed,
                    fef_status_string, load_library)
 
 

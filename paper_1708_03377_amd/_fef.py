@@ -29,7 +29,7 @@ PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
 
 Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
-Q_NSLOT, Q_NENTRIES, Q_MASKED_WS_BYTES, Q_SURR_WS_BYTES = 13, 14, 15, 16
+Q_NSLOT, Q_NENTRIES, Q_MASKED_WS_BYTES, Q_SURR_WS_BYTES, Q_BPACK_ELEMS = 13, 14, 15, 16, 17
 
 MLP_NIN, MLP_NHID, MLP_NPARAM, MLP_STRIDE, MLP_NSTATS = 17, 128, 18945, 18952, 36
 
@@ -41,7 +41,8 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_autotune", "fef_pair_energies_masked", "fef_coupling_modes",
                 "fef_fragment_invariants", "fef_pair_features", "fef_column_stats",
                 "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
-                "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_status_string")
+                "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
+                "fef_scf_step_packed", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -62,7 +63,8 @@ class SystemDesc(ctypes.Structure):
 class PassArgs(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("B", "G", "F0", "htilde", "C0", "eps0", "C", "eps", "D", "dD_max", "flags",
-                 "ops", "E2_pair", "E2_total", "ws")] + [("ws_bytes", ctypes.c_size_t)]
+                 "ops", "E2_pair", "E2_total", "ws")] + [("ws_bytes", ctypes.c_size_t),
+                                                         ("Bp", ctypes.c_void_p)]
 
 
 _lib = None
@@ -105,6 +107,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                                        vp, vp, sz, vp]
     lib.fef_mlp_train_ws_bytes.argtypes = [i32, i32, ctypes.POINTER(i64)]
     lib.fef_surrogate_select.argtypes = [vp, vp, i32, vp, vp, f64, f64, vp, vp, vp]
+    lib.fef_pack_coefficients.argtypes = [vp, vp, vp, vp]
+    lib.fef_scf_step_packed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fef_status_string.argtypes = [i32]
     lib.fef_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -239,9 +243,9 @@ class Graph:
 
 
 def fef_graph_create(plan, niter, prec, B, G, F0, htilde, C0, eps0, C, eps, D, dD_max, flags,
-                     ops, E2_pair, E2_total, ws) -> Graph:
-    bufs = (B, G, F0, htilde, C0, eps0, C, eps, D, dD_max, flags, ops, E2_pair, E2_total, ws)
-    a = PassArgs(*[_ptr(t) for t in bufs], _nbytes(ws))
+                     ops, E2_pair, E2_total, ws, Bp=None) -> Graph:
+    bufs = (B, G, F0, htilde, C0, eps0, C, eps, D, dD_max, flags, ops, E2_pair, E2_total, ws, Bp)
+    a = PassArgs(*[_ptr(t) for t in bufs[:-1]], _nbytes(ws), _ptr(Bp))
     h = ctypes.c_void_p()
     _check("fef_graph_create", load_library().fef_graph_create(plan.handle, ctypes.byref(a),
                                                                niter, prec, ctypes.byref(h)))
@@ -317,3 +321,14 @@ def fef_surrogate_select(plan, U, nmember, stats, W, r_exact, threshold, E2_pair
     _check("fef_surrogate_select", load_library().fef_surrogate_select(
         plan.handle, _ptr(U), nmember, _ptr(stats), _ptr(W), float(r_exact), float(threshold),
         _ptr(E2_pair), _ptr(select), _stream(stream)))
+
+
+def fef_pack_coefficients(plan, B, Bp, stream=None):
+    _check("fef_pack_coefficients", load_library().fef_pack_coefficients(
+        plan.handle, _ptr(B), _ptr(Bp), _stream(stream)))
+
+
+def fef_scf_step_packed(plan, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, stream=None):
+    _check("fef_scf_step_packed", load_library().fef_scf_step_packed(
+        plan.handle, _ptr(Bp), _ptr(G), _ptr(F0), _ptr(htilde), _ptr(C), _ptr(eps), _ptr(D),
+        _ptr(dD_max), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))

@@ -27,7 +27,7 @@ void free_plan(fef_plan_s* p) {
   void* ptrs[] = {p->d_frag, p->d_pair, p->d_slot_pair, p->d_ht, p->d_ht_fused, p->d_ht_generic,
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
-                  p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist};
+                  p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist, p->d_off_Bp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -296,6 +296,16 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     e = upload(&p->d_gfrag, std::vector<FragInfo>{g});
   }
   if (e == hipSuccess) e = upload(&p->d_glist, std::vector<int32_t>{0});
+  if (e == hipSuccess) {
+    std::vector<int64_t> offp(std::max(d->nfrag, 1), 0);
+    int64_t o = 0;
+    for (int f = 0; f < d->nfrag; ++f) {
+      offp[f] = o;
+      o += (int64_t)p->frag[f].naux * p->frag[f].nbf * (p->frag[f].nbf + 1) / 2;
+    }
+    p->nBp = o;
+    e = upload(&p->d_off_Bp, offp);
+  }
   if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
   *out = p;
   return FEF_OK;
@@ -331,6 +341,7 @@ fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* ou
     case FEF_Q_NENTRIES: *out = p->tiles[prec].nentries; break;
     case FEF_Q_MASKED_WS_BYTES: *out = masked_ws_bytes(*p, prec); break;
     case FEF_Q_SURR_WS_BYTES: *out = surr_ws_bytes(*p); break;
+    case FEF_Q_BPACK_ELEMS: *out = p->nBp; break;
     default: return FEF_E_ARG;
   }
   return FEF_OK;
@@ -394,13 +405,13 @@ fef_status fef_coulomb_field(fef_plan p, const double* B, const double* G, const
                                  static_cast<hipStream_t>(stream)));
 }
 
-fef_status fef_scf_step(fef_plan p, const double* B, const double* G, const double* F0,
-                        const double* htilde, double* C, double* eps, double* D,
-                        double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
-                        void* stream) {
+static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, const double* G,
+                                const double* F0, const double* htilde, double* C, double* eps,
+                                double* D, double* dD_max, int32_t* flags, void* ws,
+                                size_t ws_bytes, void* stream) {
   if (!p) return FEF_E_ARG;
   if (!dD_max || !flags) return FEF_E_ARG;
-  if (p->nfrag > 0 && (!B || !G || !F0 || !C || !eps)) return FEF_E_ARG;
+  if (p->nfrag > 0 && (!(B || Bp) || !G || !F0 || !C || !eps)) return FEF_E_ARG;
   if ((int64_t)ws_bytes < scf_ws_bytes(*p) || !ws) return FEF_E_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* wd = static_cast<double*>(ws);
@@ -412,10 +423,34 @@ fef_status fef_scf_step(fef_plan p, const double* B, const double* G, const doub
   double* eigws = F + 2 * std::max<int64_t>(p->nC, 1);
   hipError_t e = launch_density(*p, C, Dold, dD_max, st);
   if (e == hipSuccess && p->nfrag > 0)
-    e = launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
+    e = Bp ? launch_field_packed(*p, Bp, G, Dold, F0, htilde, F, wd, wphi, st)
+           : launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, F, Dold, C, eps, Dnew, dD_max, flags, eigws, st);
   return hip_status(e);
+}
+
+fef_status fef_scf_step(fef_plan p, const double* B, const double* G, const double* F0,
+                        const double* htilde, double* C, double* eps, double* D,
+                        double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                        void* stream) {
+  return scf_step_impl(p, B, nullptr, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
+                       stream);
+}
+
+fef_status fef_pack_coefficients(fef_plan p, const double* B, double* Bp, void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (p->nfrag > 0 && (!B || !Bp)) return FEF_E_ARG;
+  return hip_status(launch_pack_coefficients(*p, B, Bp, static_cast<hipStream_t>(stream)));
+}
+
+fef_status fef_scf_step_packed(fef_plan p, const double* Bp, const double* G, const double* F0,
+                               const double* htilde, double* C, double* eps, double* D,
+                               double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                               void* stream) {
+  if (p && p->nfrag > 0 && !Bp) return FEF_E_ARG;
+  return scf_step_impl(p, nullptr, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
+                       stream);
 }
 
 }  // extern "C"

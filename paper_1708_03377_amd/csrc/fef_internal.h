@@ -125,6 +125,9 @@ struct fef_plan_s {
   int32_t* d_eig_mid = nullptr;
   int32_t* d_eig_large = nullptr;
   int64_t nbr_total = 0;
+  // packed (upper-triangle) coefficient pool: per-fragment offsets
+  int64_t nBp = 0;
+  int64_t* d_off_Bp = nullptr;
   // G_{0,0} posed as one "fragment" for the eigensolver (coupling modes)
   fef::FragInfo* d_gfrag = nullptr;
   int32_t* d_glist = nullptr;
@@ -152,6 +155,11 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
 hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, const double* F,
                            const double* Dold, double* C, double* eps, double* Dnew,
                            double* dmax, int32_t* flags, double* ws_eig, hipStream_t st);
+hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
+                                    hipStream_t st);
+hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
+                               const double* D, const double* F0, const double* htilde,
+                               double* out, double* ws_d, double* ws_phi, hipStream_t st);
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st);
 

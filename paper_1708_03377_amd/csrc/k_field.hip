@@ -187,6 +187,124 @@ __global__ __launch_bounds__(256) void jbuild_kernel(const FragInfo* __restrict_
   if (e + 1 < nn) out[o + 1] = v1;
 }
 
+// ---------------------------------------------------------------------------
+// Packed coefficients: B^x[P] is symmetric, so only its upper triangle
+// (mu <= nu, row-major, nbf (nbf + 1) / 2 numbers per slice) is kept.  The
+// moments then weight off-diagonal entries by 2 and the J build writes both
+// mirror images, halving the bytes both kernels stream per SCF step.
+__device__ inline void tri_row_col(int k, int n, int& mu, int& nu) {
+  const double b = 2.0 * n + 1.0;
+  int m = (int)((b - sqrt(b * b - 8.0 * (double)k)) * 0.5);
+  if (m < 0) m = 0;
+  if (m > n - 1) m = n - 1;
+  while (m > 0 && m * n - m * (m - 1) / 2 > k) --m;
+  while (m + 1 < n && (m + 1) * n - (m + 1) * m / 2 <= k) ++m;
+  mu = m;
+  nu = m + (k - (m * n - m * (m - 1) / 2));
+}
+
+__global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* __restrict__ frag,
+                                                                const int64_t* __restrict__ off_Bp,
+                                                                const double* __restrict__ B,
+                                                                double* __restrict__ Bp) {
+  const FragInfo fi = frag[blockIdx.x];
+  const int n = fi.nbf, nt = n * (n + 1) / 2;
+  const int64_t nn = (int64_t)n * n;
+  const int64_t total = (int64_t)fi.naux * nt;
+  const double* b = B + fi.off_B;
+  double* bp = Bp + off_Bp[blockIdx.x];
+  for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.y * blockDim.x) {
+    const int P = (int)(e / nt), k = (int)(e - (e / nt) * nt);
+    int mu, nu;
+    tri_row_col(k, n, mu, nu);
+    bp[e] = b[P * nn + (int64_t)mu * n + nu];
+  }
+}
+
+// d^x_Q from the packed slices (each wave four Q, sixteen Q per block).
+__global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
+                                                             const int64_t* __restrict__ off_Bp,
+                                                             const double* __restrict__ Bp,
+                                                             const double* __restrict__ D,
+                                                             double* __restrict__ dmom) {
+  const FragInfo fi = frag[blockIdx.x];
+  const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQ;
+  if (q0 >= fi.naux) return;
+  const int lane = threadIdx.x & 63;
+  const int nq = min(kMomQ, fi.naux - q0);
+  const int n = fi.nbf, nt = n * (n + 1) / 2;
+  const double* b = Bp + off_Bp[blockIdx.x] + (int64_t)q0 * nt;
+  const double* d = D + fi.off_C;
+  double acc[kMomQ] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = lane; k < nt; k += 64) {
+    int mu, nu;
+    tri_row_col(k, n, mu, nu);
+    const double dv = (mu == nu ? 1.0 : 2.0) * d[mu * n + nu];
+#pragma unroll
+    for (int q = 0; q < kMomQ; ++q)
+      if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dv, acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kMomQ; ++q) {
+    const double t = wave_sum(acc[q]);
+    if (lane == 0 && q < nq) dmom[fi.off_aux + q0 + q] = t;
+  }
+}
+
+// out = F0 + h~ + 2 sum_P B[P] phi_P from the packed slices, both mirror
+// elements written.
+__global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __restrict__ frag,
+                                                            const int64_t* __restrict__ off_Bp,
+                                                            const double* __restrict__ Bp,
+                                                            const double* __restrict__ phi,
+                                                            const double* __restrict__ F0,
+                                                            const double* __restrict__ htilde,
+                                                            double* __restrict__ out) {
+  const FragInfo fi = frag[blockIdx.x];
+  const int n = fi.nbf, nt = n * (n + 1) / 2;
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  const double* b = Bp + off_Bp[blockIdx.x] + k;
+  const double* ph = phi + fi.off_aux;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int P = 0; P < fi.naux; ++P) acc = fma(b[(int64_t)P * nt], ph[P], acc);
+  int mu, nu;
+  tri_row_col(k, n, mu, nu);
+  const double j2 = 2.0 * acc;
+  const int64_t o1 = fi.off_C + (int64_t)mu * n + nu, o2 = fi.off_C + (int64_t)nu * n + mu;
+  double v1 = j2, v2 = j2;
+  if (F0) { v1 += F0[o1]; v2 += F0[o2]; }
+  if (htilde) { v1 += htilde[o1]; v2 += htilde[o2]; }
+  out[o1] = v1;
+  if (mu != nu) out[o2] = v2;
+}
+
+hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
+                                    hipStream_t st) {
+  if (p.nfrag == 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_coefficients_kernel, dim3(p.nfrag, 8), dim3(256), 0, st, p.d_frag,
+                     p.d_off_Bp, B, Bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
+                               const double* D, const double* F0, const double* htilde,
+                               double* out, double* ws_d, double* ws_phi, hipStream_t st) {
+  hipLaunchKernelGGL(moments_packed_kernel,
+                     dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)), dim3(256), 0, st,
+                     p.d_frag, p.d_off_Bp, Bp, D, ws_d);
+  const int etot = p.naux_cls_off.back();
+  hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
+                     p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
+                     p.d_naux_cls_off, ws_d, ws_phi);
+  const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
+  hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + 255) / 256), dim3(256), 0, st,
+                     p.d_frag, p.d_off_Bp, Bp, ws_phi, F0, htilde, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* dD_max,
                           hipStream_t st) {
   if (p.nfrag == 0) {

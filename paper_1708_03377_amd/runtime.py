@@ -85,9 +85,25 @@ class Context:
                        self.stream())
         return self.dD_max
 
+    def packed_coefficients(self):
+        """The upper-triangle copy of B (packed on first use)."""
+        if getattr(self, "_Bp", None) is None:
+            self._Bp = self.torch.empty(max(self._q(F.Q_BPACK_ELEMS), 1),
+                                        dtype=self.torch.float64, device=self.device)
+            F.fef_pack_coefficients(self.plan, self.B, self._Bp, self.stream())
+        return self._Bp
+
+    def scf_step_packed(self, D_out=None):
+        F.fef_scf_step_packed(self.plan, self.packed_coefficients(), self.G, self.F0,
+                              self.htilde, self.C, self.eps,
+                              self.D if D_out is None else D_out, self.dD_max, self.flags,
+                              self.ws, self.stream())
+        return self.dD_max
+
     def scf(self, niter: int):
+        """niter SCF steps on the packed coefficients (as the captured pass)."""
         for _ in range(niter):
-            self.scf_step()
+            self.scf_step_packed()
 
     def graph(self, niter: int, prec: int, from_start: bool = True):
         """A captured FEF pass: [reset to the generated orbitals], niter SCF
@@ -96,7 +112,7 @@ class Context:
                                   self.C0 if from_start else None,
                                   self.eps0 if from_start else None, self.C, self.eps, self.D,
                                   self.dD_max, self.flags, self.ops_for(prec), self.E2_pair,
-                                  self.E2_total, self.ws)
+                                  self.E2_total, self.ws, self.packed_coefficients())
 
     def launch(self, graph):
         F.fef_graph_launch(graph, self.stream())

@@ -239,3 +239,30 @@ def test_autotune_keeps_results(torch):
         assert us > 0
         E2 = ctx.pair_energies(PREC[prec])[0].cpu().numpy()
         assert np.max(np.abs(E2 - ref)) <= (TOL_PAIR_F64 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("which,niter", [("config0", 3), ("ragged", 2), ("two_class", 2)])
+def test_packed_scf_matches_oracle(torch, which, niter):
+    """SCF steps on the packed (upper-triangle) coefficients against the
+    oracle: orbital energies and densities within 1e-10 at every step."""
+    sysm = {"ragged": ragged_system, "two_class": two_class_system,
+            "config0": lambda: fefgen.make_system(0)}[which]()
+    ctx = ctx_for(sysm)
+    Bp = ctx.packed_coefficients().cpu().numpy()
+    # the packed pool is the upper triangle of every slice, fragments in order
+    o = 0
+    for f in range(sysm.nfrag):
+        n = int(sysm.nbf[f]); iu = np.triu_indices(n)
+        ref = np.stack([b[iu] for b in sysm.B_of(f)]).ravel()
+        np.testing.assert_array_equal(Bp[o:o + ref.size], ref)
+        o += ref.size
+    C, e = sysm.C.copy(), sysm.eps.copy()
+    for it in range(niter):
+        dmax = float(ctx.scf_step_packed().cpu()[0])
+        C, e, Dl, odmax, ok = ofef.scf_step(sysm, C, e)
+        assert abs(dmax - odmax) <= 1e-10
+        np.testing.assert_allclose(ctx.eps.cpu().numpy(), e, rtol=0, atol=1e-10)
+        D = ctx.D.cpu().numpy()
+        oc = sysm.off_C
+        for f in range(sysm.nfrag):
+            np.testing.assert_allclose(D[oc[f]:oc[f + 1]], Dl[f].ravel(), rtol=0, atol=1e-10)

@@ -105,6 +105,9 @@ def test_surrogate_entry_points_reject_bad_arguments():
                                   None) == F.FEF_E_ARG
     assert lib.fef_surrogate_select(None, None, 5, None, None, 0.0, 0.0, None, None,
                                     None) == F.FEF_E_ARG
+    assert lib.fef_pack_coefficients(None, None, None, None) == F.FEF_E_ARG
+    assert lib.fef_scf_step_packed(None, None, None, None, None, None, None, None, None, None,
+                                   None, 0, None) == F.FEF_E_ARG
 
 
 def test_mlp_layout_constants_match_header():
