@@ -63,4 +63,19 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
             (unsigned long long)__double_as_longlong(v));
 }
 
+
+// Next work item of the grouped persistent queue (8 counters at head):
+// the caller's home group first, then the others in turn; -1 when all are
+// exhausted.  Called by one thread of the workgroup.
+__device__ inline int32_t pull_item(int32_t* head, const int32_t* grp_off, int home) {
+  for (int k = 0; k < 8; ++k) {
+    const int g = (home + k) & (8 - 1);
+    const int32_t cnt = grp_off[g + 1] - grp_off[g];
+    if (cnt <= 0 || __atomic_load_n(&head[g], __ATOMIC_RELAXED) >= cnt) continue;
+    const int32_t i = atomicAdd(&head[g], 1);
+    if (i < cnt) return grp_off[g] + i;
+  }
+  return -1;
+}
+
 }  // namespace fef

@@ -74,12 +74,20 @@ struct OpsGeom {
   int pw;           // plane width (split modes)
 };
 
+// Work items come in kQueues groups of contiguous x-blocks (locality order,
+// about equal work each); group g's items are items[grp_off[g] ..
+// grp_off[g + 1]), longest first.  A workgroup serves the group of its XCD
+// first (workgroups are dealt to the XCDs round robin) and then helps the
+// others, so neighbouring x-blocks, which stream mostly the same y tiles,
+// run on one XCD and share its L2.
+constexpr int kQueues = 8;
 struct TileSet {
   int32_t xb = 0, yc = 0;
   int64_t nitems = 0, nentries = 0, nxblocks = 0;
   WorkItem* d_items = nullptr;
   Entry* d_entries = nullptr;
   XBlock* d_xblocks = nullptr;
+  int32_t* d_grp_off = nullptr;  // [kQueues + 1]
 };
 
 }  // namespace fef

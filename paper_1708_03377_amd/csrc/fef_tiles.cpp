@@ -14,8 +14,9 @@
 // 4. Tiles (per precision mode): x units (fragment, row tile) taken in
 //    locality order are grouped xb at a time into x-blocks; each block's
 //    entries are the union of its units' partners (column tiles), in locality
-//    order; entries are chunked into work items of at most yc, and the items
-//    are sorted longest first (LPT) for the persistent queue.
+//    order; entries are chunked into work items of at most yc; the items are
+//    split into eight runs of x-blocks of about equal work (one queue per
+//    XCD), each sorted longest first (LPT).
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -117,6 +118,7 @@ void free_tiles(TileSet& t) {
   if (t.d_items) (void)hipFree(t.d_items);
   if (t.d_entries) (void)hipFree(t.d_entries);
   if (t.d_xblocks) (void)hipFree(t.d_xblocks);
+  if (t.d_grp_off) (void)hipFree(t.d_grp_off);
   t = TileSet();
 }
 
@@ -190,8 +192,31 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
     const int32_t cnt = (int32_t)entries.size() - first;
     for (int32_t e0 = 0; e0 < cnt; e0 += yc) items.push_back({bid, first + e0, std::min(yc, cnt - e0), 0});
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const WorkItem& a, const WorkItem& b) { return a.ne > b.ne; });
+  // queue groups: contiguous runs of items (x-blocks in locality order) of
+  // about equal total work, then longest first inside each group
+  std::vector<int32_t> grp(items.size());
+  {
+    int64_t total = 0;
+    for (const auto& it : items) total += it.ne;
+    int64_t before = 0;
+    for (size_t i = 0; i < items.size(); ++i) {
+      grp[i] = total > 0 ? (int32_t)std::min<int64_t>(kQueues - 1, before * kQueues / total) : 0;
+      before += items[i].ne;
+    }
+  }
+  std::vector<int32_t> order(items.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return grp[a] != grp[b] ? grp[a] < grp[b] : items[a].ne > items[b].ne;
+  });
+  std::vector<WorkItem> sorted(items.size());
+  std::vector<int32_t> grp_off(kQueues + 1, 0);
+  for (size_t i = 0; i < order.size(); ++i) {
+    sorted[i] = items[order[i]];
+    ++grp_off[grp[order[i]] + 1];
+  }
+  for (int g = 0; g < kQueues; ++g) grp_off[g + 1] += grp_off[g];
+  items.swap(sorted);
 
   TileSet t;
   t.xb = xb;
@@ -202,6 +227,7 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
   hipError_t e = upload_vec(&t.d_items, items);
   if (e == hipSuccess) e = upload_vec(&t.d_entries, entries);
   if (e == hipSuccess) e = upload_vec(&t.d_xblocks, blocks);
+  if (e == hipSuccess) e = upload_vec(&t.d_grp_off, grp_off);
   if (e != hipSuccess) { free_tiles(t); return e; }
   free_tiles(p.tiles[prec]);
   p.tiles[prec] = t;

@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
-    int32_t* __restrict__ head, const char* __restrict__ ops, int prec, int kpad,
+    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops, int prec, int kpad,
     const double* __restrict__ gap, double* __restrict__ partial) {
   typedef typename Mfma<T>::acc_t acc_t;
   typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -62,11 +62,11 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
   const int r0 = (wave >> 1) * 48, c0 = (wave & 1) * 48;
   const int tot = kpad * kRowCh;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+    if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
     const int32_t it = s_item;
     __syncthreads();
-    if (it >= nitems) break;
+    if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
     if (ne == 0) continue;  // an item emptied by a pair mask
     const int fxi = xblocks[xbid].f[0];
@@ -144,7 +144,9 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
   }
 }
 
-__global__ void reset_head_kernel(int32_t* head) { *head = 0; }
+__global__ void reset_head_kernel(int32_t* head) {
+  for (int g = 0; g < kQueues; ++g) head[g] = 0;
+}
 
 // Pair mask: copies every work item's entries, in order, into the same
 // positions of a second table, keeping only the units whose pair is selected
@@ -304,7 +306,7 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
 #define FEF_PLAIN(T, KS)                                                                        \
   hipLaunchKernelGGL((pair_plain_kernel<T, KS>), grid, dim3(256), lds, st, p.d_frag, p.d_pair,  \
                      p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,             \
-                     head, o, (int)prec, kpad, gap, partial)
+                     head, t.d_grp_off, o, (int)prec, kpad, gap, partial)
         if (f64) {
           if (kpad == 72) FEF_PLAIN(double, 18); else if (kpad == 8) FEF_PLAIN(double, 2);
           else FEF_PLAIN(double, 0);

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
-    int32_t* __restrict__ head, const char* __restrict__ ops, int prec, int pw,
+    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops, int prec, int pw,
     const double* __restrict__ gap, double* __restrict__ partial) {
   constexpr int NT = 512, NW = 8;
   constexpr int WPU = NW / XB;
@@ -165,7 +165,10 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
   __shared__ float Gy[2][kTile];
   __shared__ double red[2][NW];
   __shared__ int32_t s_item;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wave index is uniform across a wave: readfirstlane lets the
+  // per-entry metadata come through scalar loads (lgkmcnt), so using it never
+  // waits on the in-order vector-memory counter of the tile prefetch
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int unit = wave / WPU, sub = wave % WPU;
   const int r0 = XB == 4 ? sub * 48 : (sub >> 1) * 48;
@@ -185,11 +188,11 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     yoff[c] = seg < 3 ? (seg == 1 ? pw : 0) + off : 2 * pw;
   }
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
+    if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
     const int32_t it = s_item;
     __syncthreads();
-    if (it >= nitems) break;
+    if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
     if (ne == 0) continue;  // an item emptied by a pair mask
     const int fxi = xblocks[xbid].f[unit];
@@ -216,7 +219,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
     }
     u16x8 pf[NPF];
-    float pg = 0.0f;
+    double pg = 0.0;  // converted when stored, so the prefetch is not waited on early
 #define FEF_ISSUE(E)                                                                            \
   {                                                                                             \
     const int y_ = entries[E].y, nt_ = entries[E].nt;                                           \
@@ -224,9 +227,9 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
                       (int64_t)nt_ * tile_ch;                                                   \
     _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
       const int c_ = threadIdx.x + NT * k_;                                                     \
-      if (c_ < tile_ch) pf[k_] = R_[c_];                                                        \
+      pf[k_] = R_[c_ < tile_ch ? c_ : tile_ch - 1];                                             \
     }                                                                                           \
-    if (threadIdx.x < kTile) pg = (float)gap[frag[y_].off_gap + nt_ * kTile + threadIdx.x];     \
+    pg = gap[frag[y_].off_gap + nt_ * kTile + (threadIdx.x < kTile ? threadIdx.x : kTile - 1)]; \
   }
 #define FEF_STORE(B)                                                                            \
   {                                                                                             \
@@ -235,7 +238,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       const int c_ = threadIdx.x + NT * k_;                                                     \
       if (c_ < tile_ch) d_[c_] = pf[k_];                                                        \
     }                                                                                           \
-    if (threadIdx.x < kTile) Gy[B][threadIdx.x] = pg;                                           \
+    if (threadIdx.x < kTile) Gy[B][threadIdx.x] = (float)pg;                                    \
   }
     FEF_ISSUE(e0)
     FEF_STORE(0)
@@ -243,8 +246,15 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     const int end = e0 + ne;
     for (int e = e0; e < end; ++e) {
       const int cur = (e - e0) & 1;
-      if (e + 1 < end) FEF_ISSUE(e + 1)
+      // this entry's metadata (scalar loads) before the next tile's prefetch
       const int slot = entries[e].slot[unit];
+      double pscale = 0.0;
+      if (sub == 0 && slot >= 0) {
+        const double s = pairs[slot_pair[slot]].s;
+        const double sc = sx * hdr[2 * entries[e].y + 1];
+        pscale = 4.0 * s * s * sc * sc;
+      }
+      if (e + 1 < end) FEF_ISSUE(e + 1)
       double mine = 0.0;
       if (slot >= 0) {
         const uint16_t* Yb = Ys + cur * kTile * xs + (c0 + li) * xs;
@@ -272,9 +282,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       if (sub == 0 && lane == 0 && slot >= 0) {
         double t = 0.0;
         for (int q = 0; q < WPU; ++q) t += red[cur][unit * WPU + q];
-        const double s = pairs[slot_pair[slot]].s;
-        const double sc = sx * hdr[2 * entries[e].y + 1];
-        partial[slot] = 4.0 * s * s * sc * sc * t;
+        partial[slot] = pscale * t;
       }
     }
 #undef FEF_ISSUE
@@ -295,7 +303,7 @@ static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds
   case N:                                                                                         \
     hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(512), lds, st, p.d_frag,       \
                        p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,                      \
-                       (int32_t)t.nitems, head, o, prec, pw, gap, partial);                       \
+                       (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);          \
     break;
     FEF_NCH(1) FEF_NCH(2) FEF_NCH(3) FEF_NCH(4) FEF_NCH(5) FEF_NCH(6) FEF_NCH(7) FEF_NCH(8)
 #undef FEF_NCH
