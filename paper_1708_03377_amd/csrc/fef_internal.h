@@ -44,7 +44,9 @@ struct PairInfo {
 // Pair-kernel work decomposition: an x-block holds up to kMaxXB x units
 // (fragment, row tile); its entries list every streamed y tile (fragment,
 // column tile) that pairs with at least one unit, with the unit's partial
-// slot (-1: no pair).  A work item is a contiguous range of one block's
+// slot (-1: no pair) and, resolved on the host so that a kernel reads them in
+// one round of scalar loads, the tile's operand and gap offsets and each
+// unit's coupling s_xy.  A work item is a contiguous range of one block's
 // entries.
 struct XBlock {
   int32_t f[kMaxXB];
@@ -53,6 +55,10 @@ struct XBlock {
 struct Entry {
   int32_t y, nt;
   int32_t slot[kMaxXB];
+  int32_t ld_y, pad;    // leading dimension of y's operand
+  int64_t off_R;        // byte offset of the y tile in this mode's operand pool
+  int64_t off_gap;      // offset of the y tile's gaps in the gap pool
+  double s[kMaxXB];     // s_xy of each unit's pair (0 without a pair)
 };
 struct WorkItem {
   int32_t xblock, e0, ne, pad;

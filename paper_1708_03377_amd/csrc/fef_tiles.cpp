@@ -158,7 +158,10 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
   std::vector<XBlock> blocks;
   std::vector<Entry> entries;
   std::vector<WorkItem> items;
-  struct Cand { int32_t rk, y, nt, u, slot; };
+  struct Cand { int32_t rk, y, nt, u, slot; double s; };
+  const bool plain = prec == FEF_F64 || prec == FEF_F32;
+  const int64_t elem = p.geom[prec].elem_bytes;
+  const int64_t xs = 2 * (int64_t)p.geom[prec].pw + 8;
   for (size_t u0 = 0; u0 < units.size(); u0 += xb) {
     XBlock blk;
     for (int u = 0; u < kMaxXB; ++u) { blk.f[u] = -1; blk.mt[u] = 0; }
@@ -170,7 +173,8 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
       for (const auto& yp : part[un.f]) {
         const PairInfo& pr = p.pairs[yp.second];
         for (int nt = 0; nt < pr.nty; ++nt)
-          c.push_back({p.rank[yp.first], yp.first, nt, u, pr.slot_first + un.mt * pr.nty + nt});
+          c.push_back({p.rank[yp.first], yp.first, nt, u, pr.slot_first + un.mt * pr.nty + nt,
+                       pr.s});
       }
     }
     std::sort(c.begin(), c.end(), [](const Cand& a, const Cand& b) {
@@ -181,11 +185,22 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
     const int32_t first = (int32_t)entries.size();
     for (size_t i = 0; i < c.size();) {
       Entry e;
+      std::memset(&e, 0, sizeof(e));
       e.y = c[i].y;
       e.nt = c[i].nt;
-      for (int u = 0; u < kMaxXB; ++u) e.slot[u] = -1;
+      const FragInfo& fy = p.frag[e.y];
+      e.ld_y = (int32_t)fy.ld;
+      // plain modes: column block nt of [kpad][ld]; split modes: row block
+      // nt of [ld][2 pw + 8]
+      e.off_R = fy.off_R[prec] + (plain ? (int64_t)e.nt * kTile * elem
+                                        : (int64_t)e.nt * kTile * xs * elem);
+      e.off_gap = fy.off_gap + (int64_t)e.nt * kTile;
+      for (int u = 0; u < kMaxXB; ++u) { e.slot[u] = -1; e.s[u] = 0.0; }
       size_t j = i;
-      for (; j < c.size() && c[j].y == c[i].y && c[j].nt == c[i].nt; ++j) e.slot[c[j].u] = c[j].slot;
+      for (; j < c.size() && c[j].y == c[i].y && c[j].nt == c[i].nt; ++j) {
+        e.slot[c[j].u] = c[j].slot;
+        e.s[c[j].u] = c[j].s;
+      }
       entries.push_back(e);
       i = j;
     }

@@ -84,9 +84,8 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
     i32x4 pf[NPF];
     double pg = 0.0;
     auto issue = [&](int e) {
-      const int y = entries[e].y, nt = entries[e].nt;
-      const int64_t yld = frag[y].ld;
-      const T* R = reinterpret_cast<const T*>(ops + frag[y].off_R[prec]) + nt * kTile;
+      const int64_t yld = entries[e].ld_y;
+      const T* R = reinterpret_cast<const T*>(ops + entries[e].off_R);
 #pragma unroll
       for (int k = 0; k < NPF; ++k) {
         const int c = threadIdx.x + 256 * k;
@@ -95,7 +94,7 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
           pf[k] = *reinterpret_cast<const i32x4*>(R + (int64_t)kk * yld + q * kVec);
         }
       }
-      if (threadIdx.x < kTile) pg = gap[frag[y].off_gap + nt * kTile + threadIdx.x];
+      if (threadIdx.x < kTile) pg = gap[entries[e].off_gap + threadIdx.x];
     };
     issue(e0);
     for (int e = e0; e < e0 + ne; ++e) {
@@ -137,7 +136,7 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
       const double sum = weighted_tiles<sizeof(T) == 8, 3, 3>(acc, Gx + r0, Gy + c0, lane, 1.0);
       const double total = block_sum(sum, red);
       if (threadIdx.x == 0) {
-        const double s = pairs[slot_pair[slot]].s;
+        const double s = entries[e].s[0];
         partial[slot] = 4.0 * s * s * total;
       }
     }

@@ -222,14 +222,12 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     double pg = 0.0;  // converted when stored, so the prefetch is not waited on early
 #define FEF_ISSUE(E)                                                                            \
   {                                                                                             \
-    const int y_ = entries[E].y, nt_ = entries[E].nt;                                           \
-    const u16x8* R_ = reinterpret_cast<const u16x8*>(ops + frag[y_].off_R[prec]) +              \
-                      (int64_t)nt_ * tile_ch;                                                   \
+    const u16x8* R_ = reinterpret_cast<const u16x8*>(ops + entries[E].off_R);                   \
     _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
       const int c_ = threadIdx.x + NT * k_;                                                     \
       pf[k_] = R_[c_ < tile_ch ? c_ : tile_ch - 1];                                             \
     }                                                                                           \
-    pg = gap[frag[y_].off_gap + nt_ * kTile + (threadIdx.x < kTile ? threadIdx.x : kTile - 1)]; \
+    pg = gap[entries[E].off_gap + (threadIdx.x < kTile ? threadIdx.x : kTile - 1)];            \
   }
 #define FEF_STORE(B)                                                                            \
   {                                                                                             \
@@ -250,7 +248,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       const int slot = entries[e].slot[unit];
       double pscale = 0.0;
       if (sub == 0 && slot >= 0) {
-        const double s = pairs[slot_pair[slot]].s;
+        const double s = entries[e].s[unit];
         const double sc = sx * hdr[2 * entries[e].y + 1];
         pscale = 4.0 * s * s * sc * sc;
       }
@@ -258,23 +256,32 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       double mine = 0.0;
       if (slot >= 0) {
         const uint16_t* Yb = Ys + cur * kTile * xs + (c0 + li) * xs;
-        f4 acc[TI][TJ];
+        // the wave's TJ column tiles in passes of TJP, so that TI x TJP
+        // independent accumulators stay live over the whole contraction
+        constexpr int TJP = TJ < 3 ? TJ : 3;
+        double part = 0.0;
 #pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          u16x8 b[TJ];
-#pragma unroll
-          for (int j = 0; j < TJ; ++j)
-            b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoff[c]);
+        for (int jh = 0; jh < TJ / TJP; ++jh) {
+          f4 acc[TI][TJP];
 #pragma unroll
           for (int i = 0; i < TI; ++i)
 #pragma unroll
-            for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+            for (int j = 0; j < TJP; ++j) acc[i][j] = f4{0, 0, 0, 0};
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            u16x8 b[TJP];
+#pragma unroll
+            for (int j = 0; j < TJP; ++j)
+              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoff[c]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+              for (int j = 0; j < TJP; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+          }
+          part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0,
+                                             Gy[cur] + c0 + 16 * jh * TJP, lane);
         }
-        mine = wave_sum(weighted_tiles_f32<TI, TJ>(acc, Gx + unit * kTile + r0, Gy[cur] + c0, lane));
+        mine = wave_sum(part);
       }
       if (lane == 0) red[cur][wave] = mine;
       if (e + 1 < end) FEF_STORE(cur ^ 1)
