@@ -27,7 +27,8 @@ void free_plan(fef_plan_s* p) {
   void* ptrs[] = {p->d_frag, p->d_pair, p->d_slot_pair, p->d_ht, p->d_ht_fused, p->d_ht_generic,
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
-                  p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist, p->d_off_Bp};
+                  p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist, p->d_off_Bp,
+                  p->d_off_tri};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -99,7 +100,9 @@ int64_t surr_ws_bytes(const fef_plan_s& p) {
 int64_t scf_ws_bytes(const fef_plan_s& p) {
   const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
   const int64_t large = 2 * (int64_t)p.eig_large.size() * slot;
-  int64_t n = 3 * std::max<int64_t>(p.nC, 1) + large;
+  // Dold, F, Dnew [nC] each, the eigensolver slots, the weighted packed
+  // density [nTri]
+  int64_t n = 3 * std::max<int64_t>(p.nC, 1) + large + std::max<int64_t>(p.nTri, 1);
   return field_ws_bytes(p) + round_up(n * (int64_t)sizeof(double), 256);
 }
 
@@ -306,6 +309,16 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     p->nBp = o;
     e = upload(&p->d_off_Bp, offp);
   }
+  if (e == hipSuccess) {
+    std::vector<int64_t> offt(std::max(d->nfrag, 1), 0);
+    int64_t o = 0;
+    for (int f = 0; f < d->nfrag; ++f) {
+      offt[f] = o;
+      o += (int64_t)p->frag[f].nbf * (p->frag[f].nbf + 1) / 2;
+    }
+    p->nTri = o;
+    e = upload(&p->d_off_tri, offt);
+  }
   if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
   *out = p;
   return FEF_OK;
@@ -421,9 +434,11 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   double* F = Dold + std::max<int64_t>(p->nC, 1);
   double* Dnew = D ? D : F + std::max<int64_t>(p->nC, 1);
   double* eigws = F + 2 * std::max<int64_t>(p->nC, 1);
-  hipError_t e = launch_density(*p, C, Dold, dD_max, st);
+  const int64_t slot = (int64_t)(p->eig_large_max_nbf + 1) * (p->eig_large_max_nbf + 1);
+  double* Dw = eigws + 2 * (int64_t)p->eig_large.size() * slot;
+  hipError_t e = launch_density(*p, C, Dold, Bp ? Dw : nullptr, dD_max, st);
   if (e == hipSuccess && p->nfrag > 0)
-    e = Bp ? launch_field_packed(*p, Bp, G, Dold, F0, htilde, F, wd, wphi, st)
+    e = Bp ? launch_field_packed(*p, Bp, G, Dw, F0, htilde, F, wd, wphi, st)
            : launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, F, Dold, C, eps, Dnew, dD_max, flags, eigws, st);

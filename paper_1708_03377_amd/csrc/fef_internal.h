@@ -142,6 +142,8 @@ struct fef_plan_s {
   // packed (upper-triangle) coefficient pool: per-fragment offsets
   int64_t nBp = 0;
   int64_t* d_off_Bp = nullptr;
+  int64_t nTri = 0;                 // sum of nbf (nbf + 1) / 2
+  int64_t* d_off_tri = nullptr;     // per-fragment offsets of packed nbf x nbf triangles
   // G_{0,0} posed as one "fragment" for the eigensolver (coupling modes)
   fef::FragInfo* d_gfrag = nullptr;
   int32_t* d_glist = nullptr;
@@ -158,7 +160,7 @@ hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const doubl
 hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const double* eps,
                                 fef_prec prec, const int32_t* select, double* E2_pair,
                                 double* E2_total, int32_t* flags, void* ws, hipStream_t st);
-hipError_t launch_density(const fef_plan_s& p, const double* C, double* D,
+hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* Dw,
                           double* dD_max, hipStream_t st);
 hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
                         const double* D, const double* F0, const double* htilde,
@@ -172,7 +174,7 @@ hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, c
 hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
                                     hipStream_t st);
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
-                               const double* D, const double* F0, const double* htilde,
+                               const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st);
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st);

@@ -12,9 +12,13 @@
 
 namespace fef {
 
+// D = C_occ C_occ^T; optionally also its upper triangle, off-diagonal
+// entries doubled (Dw[k] = w_k D[mu][nu], the weights of the packed moments).
 __global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict__ frag,
+                                                      const int64_t* __restrict__ off_tri,
                                                       const double* __restrict__ C,
                                                       double* __restrict__ D,
+                                                      double* __restrict__ Dw,
                                                       double* __restrict__ dD_max) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && dD_max) *dD_max = 0.0;
   const FragInfo fi = frag[blockIdx.x];
@@ -26,6 +30,7 @@ __global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict
     double acc = 0.0;
     for (int j = 0; j < o; ++j) acc = fma(c[l * n + j], c[s * n + j], acc);
     d[e] = acc;
+    if (Dw && l <= s) Dw[off_tri[blockIdx.x] + l * n - l * (l - 1) / 2 + (s - l)] = (l == s ? 1.0 : 2.0) * acc;
   }
 }
 
@@ -222,11 +227,14 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
   }
 }
 
-// d^x_Q from the packed slices (each wave four Q, sixteen Q per block).
+// d^x_Q = sum_k Bp[Q][k] Dw[k] from the packed slices and the weighted
+// packed density (each wave four Q, sixteen Q per block; 16-byte loads when
+// the triangle length and the offsets are even).
 __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
                                                              const int64_t* __restrict__ off_Bp,
+                                                             const int64_t* __restrict__ off_tri,
                                                              const double* __restrict__ Bp,
-                                                             const double* __restrict__ D,
+                                                             const double* __restrict__ Dw,
                                                              double* __restrict__ dmom) {
   const FragInfo fi = frag[blockIdx.x];
   const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQ;
@@ -234,16 +242,27 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
   const int lane = threadIdx.x & 63;
   const int nq = min(kMomQ, fi.naux - q0);
   const int n = fi.nbf, nt = n * (n + 1) / 2;
-  const double* b = Bp + off_Bp[blockIdx.x] + (int64_t)q0 * nt;
-  const double* d = D + fi.off_C;
+  const int64_t ob = off_Bp[blockIdx.x] + (int64_t)q0 * nt, od = off_tri[blockIdx.x];
+  const double* b = Bp + ob;
+  const double* d = Dw + od;
   double acc[kMomQ] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = lane; k < nt; k += 64) {
-    int mu, nu;
-    tri_row_col(k, n, mu, nu);
-    const double dv = (mu == nu ? 1.0 : 2.0) * d[mu * n + nu];
+  if ((nt & 1) == 0 && (ob & 1) == 0 && (od & 1) == 0) {
+    for (int k = 2 * lane; k < nt; k += 128) {
+      const double2 dv = *reinterpret_cast<const double2*>(d + k);
 #pragma unroll
-    for (int q = 0; q < kMomQ; ++q)
-      if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dv, acc[q]);
+      for (int q = 0; q < kMomQ; ++q)
+        if (q < nq) {
+          const double2 bv = *reinterpret_cast<const double2*>(b + (int64_t)q * nt + k);
+          acc[q] = fma(bv.y, dv.y, fma(bv.x, dv.x, acc[q]));
+        }
+    }
+  } else {
+    for (int k = lane; k < nt; k += 64) {
+      const double dv = d[k];
+#pragma unroll
+      for (int q = 0; q < kMomQ; ++q)
+        if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dv, acc[q]);
+    }
   }
 #pragma unroll
   for (int q = 0; q < kMomQ; ++q) {
@@ -290,11 +309,11 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
 }
 
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
-                               const double* D, const double* F0, const double* htilde,
+                               const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st) {
   hipLaunchKernelGGL(moments_packed_kernel,
                      dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)), dim3(256), 0, st,
-                     p.d_frag, p.d_off_Bp, Bp, D, ws_d);
+                     p.d_frag, p.d_off_Bp, p.d_off_tri, Bp, Dw, ws_d);
   const int etot = p.naux_cls_off.back();
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
@@ -305,13 +324,14 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* dD_max,
-                          hipStream_t st) {
+hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* Dw,
+                          double* dD_max, hipStream_t st) {
   if (p.nfrag == 0) {
     hipLaunchKernelGGL(zero_scalar_kernel, dim3(1), dim3(1), 0, st, dD_max);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(density_kernel, dim3(p.nfrag), dim3(256), 0, st, p.d_frag, C, D, dD_max);
+  hipLaunchKernelGGL(density_kernel, dim3(p.nfrag), dim3(256), 0, st, p.d_frag, p.d_off_tri, C, D,
+                     Dw, dD_max);
   return hipGetLastError();
 }
 

@@ -77,7 +77,11 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const double* __restrict__ bov, const double* __restrict__ G,
     const int64_t* __restrict__ off_G, int P0, int kpad, int pw, double* __restrict__ w_out,
     char* __restrict__ ops) {
-  __shared__ double Bs[kSmallP * kTile];  // [P][96], zero past ov and past P (to a multiple of 4)
+  // Bs [P][kBld]: B_ov, zero past ov and past P (to a multiple of 4); the
+  // split modes later reuse it as W^T [ia][P0 + 1] for coalesced packing
+  constexpr int kBld = kTile + 1;
+  __shared__ double Bs[(kSmallP * kBld > kTile * (kSmallP + 1)) ? kSmallP * kBld
+                                                                 : kTile * (kSmallP + 1)];
   __shared__ double red[4];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
@@ -85,7 +89,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
   const int P4 = (P + 3) & ~3;
   for (int e = threadIdx.x; e < P4 * kTile; e += 256) {
     const int pp = e / kTile, ia = e - (e / kTile) * kTile;
-    Bs[e] = (pp < P && ia < ov) ? bov[fi.off_bov + (int64_t)pp * ov + ia] : 0.0;
+    Bs[pp * kBld + ia] = (pp < P && ia < ov) ? bov[fi.off_bov + (int64_t)pp * ov + ia] : 0.0;
   }
   __syncthreads();
   // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia tile),
@@ -107,7 +111,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
         const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
         const int q = 16 * qt + li;
         const double av = (pp < P && q < P0) ? g[(int64_t)pp * P0 + q] : 0.0;
-        const double bv = Bs[pp * kTile + 16 * it + li];
+        const double bv = Bs[pp * kBld + 16 * it + li];
         acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
       }
     }
@@ -129,7 +133,8 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
       }
     }
   }
-  for (int e = threadIdx.x; e < P * kTile; e += 256) bmax = fmax(bmax, fabs(Bs[e]));
+  for (int e = threadIdx.x; e < P * kTile; e += 256)
+    bmax = fmax(bmax, fabs(Bs[(e / kTile) * kBld + (e - (e / kTile) * kTile)]));
   const bool right = fi.off_R[PREC] >= 0;
   if (PREC == FEF_F64 || PREC == FEF_F32) {
     typedef typename std::conditional<PREC == FEF_F64, double, float>::type T;
@@ -154,7 +159,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
         L[(int64_t)k * fi.ld + m] = (T)0;
         if (R) R[(int64_t)k * fi.ld + m] = (T)0;
       } else if (R) {
-        R[(int64_t)k * fi.ld + m] = (T)Bs[k * kTile + m];
+        R[(int64_t)k * fi.ld + m] = (T)Bs[k * kBld + m];
       }
     }
   } else {
@@ -171,6 +176,18 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const int xs = 2 * pw + 8;
     uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
     uint16_t* R = right ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
+    // rows [ia][hi plane | lo plane]: consecutive threads take consecutive q
+    // so that the 2-byte stores of a wave are contiguous
+    if (R)
+      for (int e = threadIdx.x; e < P0 * ov; e += 256) {
+        const int ia = e / P0, q = e - (e / P0) * P0;
+        uint16_t hi, lo;
+        split2<kF16>(Bs[q * kBld + ia] * sR, hi, lo);
+        R[ia * xs + q] = hi;
+        R[ia * xs + pw + q] = lo;
+      }
+    __syncthreads();  // Bs is rewritten with W^T below
+    const int wld = P0 + 1;
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
       const int t = wave + 4 * k;
@@ -179,23 +196,18 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int q = 16 * qt + lk + 4 * r, ia = 16 * it + li;
-          if (q < P0 && ia < ov) {
-            uint16_t hi, lo;
-            split2<kF16>(acc[k][r] * sL, hi, lo);
-            L[ia * xs + q] = hi;
-            L[ia * xs + pw + q] = lo;
-          }
+          if (q < P0 && ia < ov) Bs[ia * wld + q] = acc[k][r];
         }
       }
     }
-    if (R)
-      for (int e = threadIdx.x; e < P0 * ov; e += 256) {
-        const int q = e / ov, ia = e - (e / ov) * ov;
-        uint16_t hi, lo;
-        split2<kF16>(Bs[q * kTile + ia] * sR, hi, lo);
-        R[ia * xs + q] = hi;
-        R[ia * xs + pw + q] = lo;
-      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P0 * ov; e += 256) {
+      const int ia = e / P0, q = e - (e / P0) * P0;
+      uint16_t hi, lo;
+      split2<kF16>(Bs[ia * wld + q] * sL, hi, lo);
+      L[ia * xs + q] = hi;
+      L[ia * xs + pw + q] = lo;
+    }
     // zeros: rows past ov, and the columns past P0 in each plane plus the tail
     for (int e = threadIdx.x; e < kTile * xs; e += 256) {
       const int m = e / xs, k = e - (e / xs) * xs;
