@@ -249,7 +249,9 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
       continue;
     }
     p->ht_generic.push_back(f);
-    for (int p0 = 0; p0 < fi.naux; p0 += 8) ht.push_back({f, p0, std::min(8, fi.naux - p0), 0});
+    // factor slices per task: large fragments one slice each (parallelism)
+    const int per = fi.nbf > 64 ? 1 : 8;
+    for (int p0 = 0; p0 < fi.naux; p0 += per) ht.push_back({f, p0, std::min(per, fi.naux - p0), 0});
   }
   p->ht_ntasks = (int64_t)ht.size();
   p->fuse_lds[0] = (int32_t)mx_nn;   // largest nbf^2 among small fragments

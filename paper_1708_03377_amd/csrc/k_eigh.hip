@@ -526,6 +526,219 @@ __global__ __launch_bounds__(64) void eigh_wave_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Jacobi for large fragments (48 < n <= 180): one workgroup of 1024 threads
+// per matrix.  A's upper triangle (m (m + 1) / 2 numbers, m = n rounded up to
+// even) lives in LDS; in each round every 2x2 block (rows of pair k, columns
+// of pair l, k <= l) is transformed once, A_blk <- R_k^T A_blk R_l, so every
+// stored element is written by exactly one thread.  V is kept transposed in
+// a global workspace slot (row p = column p of V), so the column update of
+// a pair touches two contiguous rows.  Warm start as above (A = C^T F C,
+// V = C), same rotation formula and stopping rule.
+__device__ inline int tri_at(int i, int j, int m) {  // packed index of (min, max)
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  return a * m - a * (a - 1) / 2 + (b - a);
+}
+__device__ inline void tri_rc(int k, int m, int& i, int& j) {
+  const double b = 2.0 * m + 1.0;
+  int r = (int)((b - sqrt(b * b - 8.0 * (double)k)) * 0.5);
+  if (r < 0) r = 0;
+  if (r > m - 1) r = m - 1;
+  while (r > 0 && r * m - r * (r - 1) / 2 > k) --r;
+  while (r + 1 < m && (r + 1) * m - (r + 1) * r / 2 <= k) ++r;
+  i = r;
+  j = r + (k - (r * m - r * (r - 1) / 2));
+}
+
+constexpr int kLargeMax = 180;
+size_t eigh_large_lds_bytes(int nmax) {
+  const int m = nmax + (nmax & 1), half = m / 2;
+  return (size_t)m * (m + 1) / 2 * sizeof(double) + 2 * (size_t)half * sizeof(double) +
+         2 * (size_t)half * sizeof(int) + (size_t)m * sizeof(double) + 2 * (size_t)m * sizeof(int);
+}
+
+__global__ __launch_bounds__(1024) void eigh_large_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
+    const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
+    double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
+    int32_t* __restrict__ flags, double* __restrict__ ws_eig, int max_n) {
+  constexpr int NT = 1024;
+  extern __shared__ double sm[];
+  __shared__ double red[NT / 64];
+  const int f = list[blockIdx.x];
+  const FragInfo fi = frag[f];
+  const int n = fi.nbf, m = n + (n & 1), half = m / 2, ntri = m * (m + 1) / 2;
+  double* Ap = sm;
+  double* cc = Ap + ntri;
+  double* ss = cc + half;
+  int* pp = reinterpret_cast<int*>(ss + half);
+  int* qq = pp + half;
+  double* lam = reinterpret_cast<double*>(qq + half);  // 2 half ints: 8-byte aligned
+  int* rank = reinterpret_cast<int*>(lam + m);
+  int* occ = rank + m;
+  const size_t slot = (size_t)(max_n + 1) * (max_n + 1);
+  double* Vt = ws_eig + (size_t)blockIdx.x * 2 * slot;  // [m][m]
+  double* T = Vt + slot;                                 // [n][n]
+  const double* Fx = F + fi.off_C;
+  const double* Cx = C + fi.off_C;
+  // T = F_sym C, then the upper triangle of A = C^T T, and V^T = C^T
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, j = e - (e / n) * n;
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) acc = fma(0.5 * (Fx[i * n + k] + Fx[k * n + i]), Cx[k * n + j], acc);
+    T[e] = acc;
+  }
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const int p = e / m, i = e - (e / m) * m;
+    Vt[e] = (p < n && i < n) ? Cx[i * n + p] : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ntri; k += NT) {
+    int i, j;
+    tri_rc(k, m, i, j);
+    double acc = 0.0;
+    if (i < n && j < n)
+      for (int q = 0; q < n; ++q) acc = fma(Cx[q * n + i], T[q * n + j], acc);
+    Ap[k] = acc;
+  }
+  __syncthreads();
+  // This thread's 2x2 blocks (at most kBlk: half (half + 1) / 2 <= 4096),
+  // fixed for the whole solve.
+  constexpr int kBlk = 4;
+  static_assert((kLargeMax / 2) * (kLargeMax / 2 + 1) / 2 <= kBlk * NT, "block table");
+  const int nblk = half * (half + 1) / 2;
+  int blk[kBlk];
+#pragma unroll
+  for (int j = 0; j < kBlk; ++j) {
+    const int b = threadIdx.x + j * NT;
+    int k = 0, l = 0;
+    if (b < nblk) tri_rc(b, half, k, l);
+    blk[j] = b < nblk ? (k | (l << 16)) : -1;
+  }
+  // V^T update map: thread = (pair group vg, column vi); the pairs
+  // vg, vg + ngrp, ... of a round, kVB of them per batch so that all their
+  // loads are in flight together.
+  constexpr int kVB = 6;
+  const int ngrp = NT / n;  // >= 5
+  const int vg = threadIdx.x / n, vi = threadIdx.x - (threadIdx.x / n) * n;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int k = threadIdx.x; k < ntri; k += NT) {
+      int i, j;
+      tri_rc(k, m, i, j);
+      const double a = Ap[k];
+      if (i == j) dia += a * a; else off += 2.0 * a * a;
+    }
+    off = block_sum(off, red);
+    dia = block_sum(dia, red);
+    if (off <= 1e-28 * dia || !(off == off)) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = threadIdx.x; k < half; k += NT) {
+        int p, q;
+        round_robin_pair(r, k, m, p, q);
+        double c, s;
+        jacobi_rotation(Ap[tri_at(p, p, m)], Ap[tri_at(q, q, m)], Ap[tri_at(p, q, m)], c, s);
+        cc[k] = c;
+        ss[k] = s;
+        pp[k] = p;
+        qq[k] = q;
+      }
+      __syncthreads();
+      // columns p, q of V (rows of V^T) of every pair: loads of a batch first
+      if (vg < ngrp)
+        for (int k0 = vg; k0 < half; k0 += kVB * ngrp) {
+          double vp[kVB], vq[kVB];
+#pragma unroll
+          for (int u = 0; u < kVB; ++u) {
+            const int k = k0 + u * ngrp;
+            if (k < half) {
+              vp[u] = Vt[(size_t)pp[k] * m + vi];
+              vq[u] = Vt[(size_t)qq[k] * m + vi];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kVB; ++u) {
+            const int k = k0 + u * ngrp;
+            if (k < half) {
+              const double c = cc[k], s = ss[k];
+              Vt[(size_t)pp[k] * m + vi] = c * vp[u] - s * vq[u];
+              Vt[(size_t)qq[k] * m + vi] = s * vp[u] + c * vq[u];
+            }
+          }
+        }
+#pragma unroll
+      for (int j = 0; j < kBlk; ++j) {
+        if (blk[j] < 0) continue;
+        const int k = blk[j] & 0xffff, l = blk[j] >> 16;
+        const int a0 = pp[k], a1 = qq[k], b0 = pp[l], b1 = qq[l];
+        const double ck = cc[k], sk = ss[k], cl = cc[l], sl = ss[l];
+        const int i00 = tri_at(a0, b0, m), i01 = tri_at(a0, b1, m);
+        const int i10 = tri_at(a1, b0, m), i11 = tri_at(a1, b1, m);
+        const double m00 = Ap[i00], m01 = Ap[i01], m10 = Ap[i10], m11 = Ap[i11];
+        const double t00 = ck * m00 - sk * m10, t01 = ck * m01 - sk * m11;
+        const double t10 = sk * m00 + ck * m10, t11 = sk * m01 + ck * m11;
+        const double n00 = cl * t00 - sl * t01, n01 = sl * t00 + cl * t01;
+        const double n10 = cl * t10 - sl * t11, n11 = sl * t10 + cl * t11;
+        Ap[i00] = n00;
+        Ap[i01] = n01;  // for k == l, (a0, a1) = (p, q) with p < q and i10 == i01
+        Ap[i11] = n11;
+        if (k != l) Ap[i10] = n10;
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order, ties broken by index
+  for (int i = threadIdx.x; i < n; i += NT) lam[i] = Ap[tri_at(i, i, m)];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double li = lam[i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = lam[j];
+      rk += (lj < li) || (lj == li && j < i);
+    }
+    rank[i] = rk;
+    if (rk < fi.nocc) occ[rk] = i;
+    eps[fi.off_eps + rk] = li;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int p = e / n, i = e - (e / n) * n;
+    C[fi.off_C + (size_t)i * n + rank[p]] = Vt[(size_t)p * m + i];
+  }
+  // occupied columns of V into LDS when they fit where A was, then D
+  const bool vo_lds = fi.nocc * n <= ntri;
+  double* Vo = Ap;  // [nocc][n]
+  if (vo_lds)
+    for (int e = threadIdx.x; e < fi.nocc * n; e += NT) {
+      const int k = e / n, i = e - (e / n) * n;
+      Vo[e] = Vt[(size_t)occ[k] * m + i];
+    }
+  __syncthreads();
+  double dmax = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int l = e / n, s = e - (e / n) * n;
+    double acc = 0.0;
+    for (int k = 0; k < fi.nocc; ++k)
+      acc = vo_lds ? fma(Vo[k * n + l], Vo[k * n + s], acc)
+                   : fma(Vt[(size_t)occ[k] * m + l], Vt[(size_t)occ[k] * m + s], acc);
+    Dnew[fi.off_C + e] = acc;
+    dmax = fmax(dmax, fabs(acc - Dold[fi.off_C + e]));
+  }
+  dmax = block_max(dmax, red);
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(dD_max, dmax);
+    if (fi.nocc > 0 && fi.nocc < n) {
+      double lh = 0.0, ll = 0.0;
+      for (int j = 0; j < n; ++j) {
+        if (rank[j] == fi.nocc - 1) lh = lam[j];
+        if (rank[j] == fi.nocc) ll = lam[j];
+      }
+      if (!(ll > lh)) atomicOr(flags, FEF_FLAG_GAP);
+    }
+  }
+}
+
 // rotation table (c, s, p, q per pair) + ranks + sorted eigenvalues
 static size_t eig_scratch_bytes(int n) {
   const int half = (n + 1) / 2;
@@ -563,7 +776,20 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        st, p.d_frag, p.d_eig_mid, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig,
                        nmax);
   }
-  if (!p.eig_large.empty()) {
+  if (!p.eig_large.empty() && p.eig_large_max_nbf <= kLargeMax) {
+    const int nmax = p.eig_large_max_nbf;
+    static bool configured = false;
+    if (!configured) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_large_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)eigh_large_lds_bytes(kLargeMax));
+      (void)hipGetLastError();
+      configured = true;
+    }
+    hipLaunchKernelGGL(eigh_large_kernel, dim3((unsigned)p.eig_large.size()), dim3(1024),
+                       eigh_large_lds_bytes(nmax), st, p.d_frag, p.d_eig_large, F, Dold, C, eps,
+                       Dnew, dD_max, flags, ws_eig, nmax);
+  } else if (!p.eig_large.empty()) {
     const int nmax = p.eig_large_max_nbf;
     hipLaunchKernelGGL((eigh_kernel<1024, 0>), dim3((unsigned)p.eig_large.size()), dim3(1024),
                        eig_scratch_bytes(nmax), st, p.d_frag, p.d_eig_large, F, Dold, C, eps,

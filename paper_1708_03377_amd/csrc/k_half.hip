@@ -252,7 +252,9 @@ __global__ __launch_bounds__(256) void ht_bov_kernel(const FragInfo* __restrict_
   }
 }
 
-// W^x[Q][ia] for Q in [8*blockIdx.y, +8).
+// W = G_{c,0}^T B_ov for the generic fragments: block (fragment, 8 q, 256
+// ia); each thread keeps the 8 q sums of its ia, so every B_ov load feeds 8
+// FMAs and the G values are broadcast.
 __global__ __launch_bounds__(256) void ht_w_kernel(const FragInfo* __restrict__ frag,
                                                    const int32_t* __restrict__ list,
                                                    const double* __restrict__ G,
@@ -260,17 +262,22 @@ __global__ __launch_bounds__(256) void ht_w_kernel(const FragInfo* __restrict__ 
                                                    const double* __restrict__ bov,
                                                    double* __restrict__ w) {
   const FragInfo fi = frag[list[blockIdx.x]];
-  if (fi.ov == 0) return;
+  const int ia = blockIdx.z * 256 + threadIdx.x;
+  if (fi.ov == 0 || ia >= fi.ov) return;
   const double* g = G + off_G[fi.cls];  // [P_c][P0]
   const double* b = bov + fi.off_bov;   // [P_c][ov]
   const int q0 = blockIdx.y * 8;
   const int nq = min(8, P0 - q0);
-  for (int e = threadIdx.x; e < nq * fi.ov; e += blockDim.x) {
-    const int q = q0 + e / fi.ov, ia = e - (e / fi.ov) * fi.ov;
-    double acc = 0.0;
-    for (int P = 0; P < fi.naux; ++P) acc = fma(g[(int64_t)P * P0 + q], b[(int64_t)P * fi.ov + ia], acc);
-    w[fi.off_w + (int64_t)q * fi.ov + ia] = acc;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int P = 0; P < fi.naux; ++P) {
+    const double bv = b[(int64_t)P * fi.ov + ia];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < nq) acc[k] = fma(g[(int64_t)P * P0 + q0 + k], bv, acc[k]);
   }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < nq) w[fi.off_w + (int64_t)(q0 + k) * fi.ov + ia] = acc[k];
 }
 
 // Operand pool, FP64 / FP32 modes: L^x = W^x and R^y = B_ov^y stored
@@ -325,7 +332,8 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
       const size_t lds = (size_t)std::max<int64_t>(p.max_on, 1) * sizeof(double);
       hipLaunchKernelGGL(ht_bov_kernel, dim3((unsigned)p.ht_ntasks), dim3(256), lds, st,
                          p.d_frag, p.d_ht, B, C, bov);
-      hipLaunchKernelGGL(ht_w_kernel, dim3(ng, (p.P0 + 7) / 8), dim3(256), 0, st, p.d_frag,
+      hipLaunchKernelGGL(ht_w_kernel, dim3(ng, (p.P0 + 7) / 8, (p.max_ov + 255) / 256), dim3(256),
+                         0, st, p.d_frag,
                          p.d_ht_generic, G, p.d_off_G, p.P0, bov, w);
     }
     switch (prec) {

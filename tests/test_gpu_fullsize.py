@@ -7,6 +7,8 @@
   final orbitals.
 * 1000 water fragments: one full SCF step of every fragment against the
   oracle (orbital energies and densities), from the generated orbitals.
+* one 150-function nucleobase in 2000 waters: one SCF step (the nucleobase
+  takes the large-matrix eigensolver) and the nucleobase's half transform.
 """
 import sys
 
@@ -93,3 +95,34 @@ def test_scf_step_full_size():
     D = ctx.D.cpu().numpy()
     Dref = np.concatenate([d.ravel() for d in Dl])
     assert np.max(np.abs(D - Dref)) <= 1e-10
+
+
+def test_nucleobase_scf_step_and_half_transform_full_size():
+    """One nucleobase (nbf 150, P 450) in 2000 waters: one SCF step of every
+    fragment against the oracle, then the half transform of the nucleobase
+    (B_ov and W) on the new orbitals."""
+    import paper_1708_03377_amd as lib
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = fefgen.make_system(2)
+    ctx = lib.Context(s)
+    dmax = float(ctx.scf_step().cpu()[0])
+    C, e, Dl, odmax, ok = ofef.scf_step(s, s.C.copy(), s.eps.copy())
+    assert abs(dmax - odmax) <= 1e-10
+    np.testing.assert_allclose(ctx.eps.cpu().numpy(), e, rtol=0, atol=1e-10)
+    D = ctx.D.cpu().numpy()
+    Dref = np.concatenate([d.ravel() for d in Dl])
+    assert np.max(np.abs(D - Dref)) <= 1e-10
+    bov = torch.zeros(ctx.sizes["bov"], dtype=torch.float64, device="cuda")
+    w = torch.zeros(ctx.sizes["w"], dtype=torch.float64, device="cuda")
+    ctx.half_transform(PREC["f64"], bov, w)
+    torch.cuda.synchronize()
+    f = 0  # the nucleobase
+    o = int(s.nocc[f]); n = int(s.nbf[f]); P = int(s.naux[f]); ov = o * (n - o)
+    ref = ofef.half_transform(s.B_of(f), s.C_of(f, ctx.C.cpu().numpy()), o).reshape(P, ov)
+    got = bov.cpu().numpy()[:P * ov].reshape(P, ov)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    refw = s.G_of(1).T @ ref
+    gotw = w.cpu().numpy()[:s.naux_class[0] * ov].reshape(-1, ov)
+    np.testing.assert_allclose(gotw, refw, rtol=0, atol=1e-12)

@@ -266,3 +266,27 @@ def test_packed_scf_matches_oracle(torch, which, niter):
         oc = sysm.off_C
         for f in range(sysm.nfrag):
             np.testing.assert_allclose(D[oc[f]:oc[f + 1]], Dl[f].ravel(), rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("solute", [(64, 12, 24), (65, 13, 24)])
+def test_scf_large_fragment(torch, solute):
+    """Fragments above 48 basis functions take the large-matrix eigensolver
+    (packed triangle in LDS); an odd size adds a decoupled padding index.
+    Orbital energies and densities against the oracle over two SCF steps, for
+    both the full and the packed coefficient paths."""
+    sysm = fefgen.make_two_class_system(31, solute, [(24, 5), (9, 2), (24, 5), (13, 6)], naux0=8)
+    for packed in (False, True):
+        ctx = ctx_for(sysm)
+        C, e = sysm.C.copy(), sysm.eps.copy()
+        for it in range(2):
+            dmax = float((ctx.scf_step_packed() if packed else ctx.scf_step()).cpu()[0])
+            C, e, Dl, odmax, ok = ofef.scf_step(sysm, C, e)
+            assert abs(dmax - odmax) <= 1e-10
+            np.testing.assert_allclose(ctx.eps.cpu().numpy(), e, rtol=0, atol=1e-10)
+            D = ctx.D.cpu().numpy()
+            oc = sysm.off_C
+            for f in range(sysm.nfrag):
+                np.testing.assert_allclose(D[oc[f]:oc[f + 1]], Dl[f].ravel(), rtol=0, atol=1e-10)
+        ref, _ = ofef.pair_energies(sysm, C, e)
+        E2, _ = ctx.energies(PREC["f64"])
+        assert np.max(np.abs(E2.cpu().numpy() - ref)) <= TOL_PAIR_F64
