@@ -28,7 +28,7 @@ void free_plan(fef_plan_s* p) {
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
                   p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist, p->d_off_Bp,
-                  p->d_off_tri};
+                  p->d_off_tri, p->d_chunk_C, p->d_chunk_Bp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -137,6 +137,9 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   for (int f = 0; f < d->nfrag; ++f) {
     if (d->nbf[f] < 1 || d->nocc[f] < 0 || d->nocc[f] > d->nbf[f]) return FEF_E_SHAPE;
     if (d->cls[f] < 0 || d->cls[f] >= d->nclass) return FEF_E_SHAPE;
+    // element indices inside one fragment's coefficient slab are 32-bit
+    if ((int64_t)d->naux[d->cls[f]] * d->nbf[f] * d->nbf[f] > (int64_t)INT32_MAX)
+      return FEF_E_UNSUPPORTED;
   }
 
   fef_plan_s* p = new (std::nothrow) fef_plan_s();
@@ -302,24 +305,48 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   }
   if (e == hipSuccess) e = upload(&p->d_glist, std::vector<int32_t>{0});
   if (e == hipSuccess) {
-    std::vector<int64_t> offp(std::max(d->nfrag, 1), 0);
+    // nfrag + 1 entries: the last is the pool size
+    std::vector<int64_t> offp(d->nfrag + 1, 0);
     int64_t o = 0;
     for (int f = 0; f < d->nfrag; ++f) {
       offp[f] = o;
       o += (int64_t)p->frag[f].naux * p->frag[f].nbf * (p->frag[f].nbf + 1) / 2;
     }
+    offp[d->nfrag] = o;
     p->nBp = o;
     e = upload(&p->d_off_Bp, offp);
   }
   if (e == hipSuccess) {
-    std::vector<int64_t> offt(std::max(d->nfrag, 1), 0);
+    std::vector<int64_t> offt(d->nfrag + 1, 0);
     int64_t o = 0;
     for (int f = 0; f < d->nfrag; ++f) {
       offt[f] = o;
       o += (int64_t)p->frag[f].nbf * (p->frag[f].nbf + 1) / 2;
     }
+    offt[d->nfrag] = o;
     p->nTri = o;
     e = upload(&p->d_off_tri, offt);
+  }
+  if (e == hipSuccess) {
+    // chunks of the density pool (nbf^2 per fragment) and of the packed pool
+    // (naux nbf (nbf + 1) / 2 per fragment), cut at fragment boundaries
+    std::vector<Chunk> cc, cb;
+    int64_t oc = 0, ob = 0;
+    for (int f = 0; f < d->nfrag; ++f) {
+      const FragInfo& fi = p->frag[f];
+      const int64_t nc = (int64_t)fi.nbf * fi.nbf;
+      const int64_t nb = (int64_t)fi.naux * fi.nbf * (fi.nbf + 1) / 2;
+      for (int64_t s = 0; s < nc; s += kDensityChunk)
+        cc.push_back({oc + s, oc + std::min<int64_t>(s + kDensityChunk, nc), f, 0});
+      for (int64_t s = 0; s < nb; s += kPackChunk)
+        cb.push_back({ob + s, ob + std::min<int64_t>(s + kPackChunk, nb), f, 0});
+      oc += nc;
+      ob += nb;
+    }
+    p->n_chunk_C = (int64_t)cc.size();
+    p->n_chunk_Bp = (int64_t)cb.size();
+    if (!cc.empty()) e = upload(&p->d_chunk_C, cc);
+    if (e == hipSuccess && !cb.empty()) e = upload(&p->d_chunk_Bp, cb);
   }
   if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
   *out = p;

@@ -98,6 +98,16 @@ struct TileSet {
 
 }  // namespace fef
 
+// [begin, end) of a flat pool, all inside fragment `frag`; the density pool
+// is cut into chunks of at most kDensityChunk elements, the packed
+// coefficient pool into chunks of at most kPackChunk.
+constexpr int kDensityChunk = 1024;
+constexpr int kPackChunk = 4096;
+struct Chunk {
+  int64_t begin, end;
+  int32_t frag, pad;
+};
+
 struct fef_plan_s {
   int device = 0;
   int32_t nfrag = 0, nclass = 0, P0 = 0;
@@ -144,6 +154,11 @@ struct fef_plan_s {
   int64_t* d_off_Bp = nullptr;
   int64_t nTri = 0;                 // sum of nbf (nbf + 1) / 2
   int64_t* d_off_tri = nullptr;     // per-fragment offsets of packed nbf x nbf triangles
+  // element chunks of the flat density pool and of the packed coefficient
+  // pool, each inside one fragment (one block per chunk)
+  int64_t n_chunk_C = 0, n_chunk_Bp = 0;
+  Chunk* d_chunk_C = nullptr;
+  Chunk* d_chunk_Bp = nullptr;
   // G_{0,0} posed as one "fragment" for the eigensolver (coupling modes)
   fef::FragInfo* d_gfrag = nullptr;
   int32_t* d_glist = nullptr;

@@ -7,48 +7,34 @@
 //   J^x      = 2 sum_P B^x[P] phi^x_P ;  F~^x = F0^x + h~^x + J^x
 // Moments and J each stream B once (HBM bound); the neighbour sum gathers
 // P-vectors of the neighbours (L2 resident).
-#include <algorithm>
-
 #include "fef_internal.h"
 #include "fef_device.h"
 
 namespace fef {
 
-// Fragment owning flat element g: the last f with off(f) <= g (offsets
-// ascending; off_of(f) returns fragment f's first element).
-template <typename OffOf>
-__device__ inline int owner_fragment(int64_t g, int nfrag, OffOf off_of) {
-  int lo = 0, hi = nfrag - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off_of(mid) <= g) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// D = C_occ C_occ^T over the flat density pool (every element of every
-// fragment, grid-stride); optionally also its upper triangle, off-diagonal
-// entries doubled (Dw[k] = w_k D[mu][nu], the weights of the packed moments).
-__global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict__ frag, int nfrag,
-                                                      int64_t nC,
+// D = C_occ C_occ^T, one block per chunk of the flat density pool;
+// optionally also its upper triangle, off-diagonal entries doubled
+// (Dw[k] = w_k D[mu][nu], the weights of the packed moments).
+__global__ __launch_bounds__(256) void density_kernel(const FragInfo* __restrict__ frag,
+                                                      const Chunk* __restrict__ chunks,
                                                       const int64_t* __restrict__ off_tri,
                                                       const double* __restrict__ C,
                                                       double* __restrict__ D,
                                                       double* __restrict__ Dw,
                                                       double* __restrict__ dD_max) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && dD_max) *dD_max = 0.0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nC;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int f = owner_fragment(g, nfrag, [&](int q) { return frag[q].off_C; });
-    const int n = frag[f].nbf, o = frag[f].nocc;
-    const int64_t oc = frag[f].off_C;
-    const int e = (int)(g - oc);
+  const Chunk ch = chunks[blockIdx.x];
+  const FragInfo fi = frag[ch.frag];
+  const int n = fi.nbf, o = fi.nocc;
+  const double* c = C + fi.off_C;
+  const int e0 = (int)(ch.begin - fi.off_C), e1 = (int)(ch.end - fi.off_C);
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
     const int l = e / n, s = e - (e / n) * n;
-    const double* c = C + oc;
     double acc = 0.0;
-    for (int j = 0; j < o; ++j) acc = fma(c[l * n + j], c[s * n + j], acc);
-    D[g] = acc;
-    if (Dw && l <= s) Dw[off_tri[f] + l * n - l * (l - 1) / 2 + (s - l)] = (l == s ? 1.0 : 2.0) * acc;
+    for (int k = 0; k < o; ++k) acc = fma(c[l * n + k], c[s * n + k], acc);
+    D[fi.off_C + e] = acc;
+    if (Dw && l <= s)
+      Dw[off_tri[ch.frag] + l * n - l * (l - 1) / 2 + (s - l)] = (l == s ? 1.0 : 2.0) * acc;
   }
 }
 
@@ -216,8 +202,9 @@ __global__ __launch_bounds__(256) void jbuild_kernel(const FragInfo* __restrict_
 // moments then weight off-diagonal entries by 2 and the J build writes both
 // mirror images, halving the bytes both kernels stream per SCF step.
 __device__ inline void tri_row_col(int k, int n, int& mu, int& nu) {
-  const double b = 2.0 * n + 1.0;
-  int m = (int)((b - sqrt(b * b - 8.0 * (double)k)) * 0.5);
+  // float guess of the row (the loops below correct it)
+  const float b = 2.0f * n + 1.0f;
+  int m = (int)((b - sqrtf(fmaxf(b * b - 8.0f * (float)k, 0.0f))) * 0.5f);
   if (m < 0) m = 0;
   if (m > n - 1) m = n - 1;
   while (m > 0 && m * n - m * (m - 1) / 2 > k) --m;
@@ -226,20 +213,23 @@ __device__ inline void tri_row_col(int k, int n, int& mu, int& nu) {
   nu = m + (k - (m * n - m * (m - 1) / 2));
 }
 
+// Bp = upper triangles of the B slices, one block per chunk of the packed pool.
 __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* __restrict__ frag,
-                                                                int nfrag, int64_t nBp,
+                                                                const Chunk* __restrict__ chunks,
                                                                 const int64_t* __restrict__ off_Bp,
                                                                 const double* __restrict__ B,
                                                                 double* __restrict__ Bp) {
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nBp;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int f = owner_fragment(g, nfrag, [&](int q) { return off_Bp[q]; });
-    const int n = frag[f].nbf, nt = n * (n + 1) / 2;
-    const int64_t e = g - off_Bp[f];
-    const int P = (int)(e / nt), k = (int)(e - (e / nt) * nt);
+  const Chunk ch = chunks[blockIdx.x];
+  const FragInfo fi = frag[ch.frag];
+  const int n = fi.nbf, nt = n * (n + 1) / 2;
+  const double* b = B + fi.off_B;
+  const int64_t base = off_Bp[ch.frag];
+  const int e0 = (int)(ch.begin - base), e1 = (int)(ch.end - base);
+  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int P = e / nt, k = e - (e / nt) * nt;
     int mu, nu;
     tri_row_col(k, n, mu, nu);
-    Bp[g] = B[frag[f].off_B + (int64_t)P * n * n + (int64_t)mu * n + nu];
+    Bp[base + e] = b[P * n * n + mu * n + nu];
   }
 }
 
@@ -319,9 +309,8 @@ __global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __re
 hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
                                     hipStream_t st) {
   if (p.nfrag == 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((p.nBp + 255) / 256, 8192);
-  hipLaunchKernelGGL(pack_coefficients_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p.d_frag,
-                     p.nfrag, p.nBp, p.d_off_Bp, B, Bp);
+  hipLaunchKernelGGL(pack_coefficients_kernel, dim3((unsigned)p.n_chunk_Bp), dim3(256), 0, st,
+                     p.d_frag, p.d_chunk_Bp, p.d_off_Bp, B, Bp);
   return hipGetLastError();
 }
 
@@ -347,9 +336,8 @@ hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, doubl
     hipLaunchKernelGGL(zero_scalar_kernel, dim3(1), dim3(1), 0, st, dD_max);
     return hipGetLastError();
   }
-  const int64_t blocks = std::min<int64_t>((p.nC + 255) / 256, 8192);
-  hipLaunchKernelGGL(density_kernel, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st,
-                     p.d_frag, p.nfrag, p.nC, p.d_off_tri, C, D, Dw, dD_max);
+  hipLaunchKernelGGL(density_kernel, dim3((unsigned)p.n_chunk_C), dim3(256), 0, st, p.d_frag,
+                     p.d_chunk_C, p.d_off_tri, C, D, Dw, dD_max);
   return hipGetLastError();
 }
 
