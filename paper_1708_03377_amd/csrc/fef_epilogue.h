@@ -43,10 +43,11 @@ __device__ inline double weighted_tiles(const AccT (&acc)[TI][TJ], const double*
 // Split-precision epilogue: FP32 weights 1/(Delta_x + Delta_y) from the
 // hardware reciprocal refined by one Newton step, r <- r (2 - d r) (error
 // about half an ulp, symmetric), FP32 squares summed over the 4 elements of
-// a tile, tile sums accumulated in FP64.
-template <int TI, int TJ>
+// a tile, tile sums accumulated in FP64.  The column gaps gy may be stored in
+// FP32 or FP64 (converted on load).
+template <int TI, int TJ, typename GyT>
 __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float* gx,
-                                            const float* gy, int lane) {
+                                            const GyT* gy, int lane) {
   const int li = lane & 15, lk = lane >> 4;
   float dx[TI][4], dy[TJ];
 #pragma unroll
@@ -54,7 +55,7 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
 #pragma unroll
     for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + 4 * lk + r];
 #pragma unroll
-  for (int j = 0; j < TJ; ++j) dy[j] = gy[16 * j + li];
+  for (int j = 0; j < TJ; ++j) dy[j] = (float)gy[16 * j + li];
   double sum = 0.0;
 #pragma unroll
   for (int i = 0; i < TI; ++i)

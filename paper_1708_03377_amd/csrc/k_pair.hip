@@ -318,7 +318,7 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
       }
       default: {
         hipError_t e = launch_split_pairs(p, ops, gap, prec, entries, items, partial, head,
-                                          persistent_grid(t.nitems, 1), st);
+                                          compute_units(), st);
         if (e != hipSuccess) return e;
       }
     }

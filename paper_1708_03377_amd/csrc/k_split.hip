@@ -135,45 +135,46 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// Persistent split-precision pair kernel (8 waves).  Work items as in the
-// plain kernel.  A workgroup serves XB x units (XB = 4: two waves per unit,
-// 48x96 each; XB = 2: four waves per unit, 48x48 each).  Every wave keeps
-// its x rows' MFMA A fragments (rows [hi|lo] of W^x, all NCH contraction
-// chunks) in registers for the whole item; the streamed y tiles (rows
-// [hi|lo] of B^y, with their gaps) pass through a double-buffered LDS stage
-// shared by all units, the next tile being fetched into registers while the
-// current one is contracted.  Two waves per SIMD let one wave's FP32
-// epilogue run beside the other's MFMA chain.  MFMA operand lane layout
-// (16x16x32): row (or column) = lane % 16, contraction indices 8 (lane / 16)
-// .. +7.
+// Persistent split-precision pair kernel.  Work items as in the plain
+// kernel.  A workgroup serves XB x units with two waves each (128 XB
+// threads; XB = 2 runs two workgroups per CU, whose barriers are
+// independent, so one workgroup's FP32 epilogue overlaps the other's MFMA
+// chains on the same SIMD).  Every wave owns 48 x rows x 96 y columns: its
+// MFMA A fragments (rows [hi|lo] of W^x, all NCH contraction chunks) stay in
+// registers for the whole item; the streamed y tiles (rows [hi|lo] of B^y)
+// and their gaps are copied from global memory straight into one of two LDS
+// buffers (global_load_lds, 16 bytes per lane) while the other buffer is
+// contracted.  The two buffers are separate LDS arrays, so the compiler
+// knows that reads of the current one never wait for the copy into the next.
+// MFMA operand lane layout (16x16x32): row (or column) = lane % 16,
+// contraction indices 8 (lane / 16) .. +7.
+constexpr int kXsMax = 2 * 80 + 8;  // row stride bound (pw <= 80)
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 template <bool kFp16, int XB, int NCH>
-__global__ __launch_bounds__(512) void pair_split_kernel(
+__global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
-    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops, int prec, int pw,
-    const double* __restrict__ gap, double* __restrict__ partial) {
-  constexpr int NT = 512, NW = 8;
-  constexpr int WPU = NW / XB;
-  constexpr int TI = 3;
-  constexpr int TJ = XB == 4 ? 6 : 3;
-  constexpr int NPF = (kTile * (2 * 80 + 8) / 8 + NT - 1) / NT;  // staging chunks per thread
-  extern __shared__ char smem[];
-  const int xs = 2 * pw + 8;  // row stride (16-bit elements) in HBM and LDS
-  uint16_t* Ys = reinterpret_cast<uint16_t*>(smem);  // [2][kTile][xs]
+    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops,
+    int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
+  constexpr int NT = 128 * XB, NW = 2 * XB;
+  constexpr int TI = 3, TJ = 6, TJP = 3;
+  __shared__ __align__(16) uint16_t YsA[kTile * kXsMax];
+  __shared__ __align__(16) uint16_t YsB[kTile * kXsMax];
+  __shared__ __align__(16) double GyA[kTile];
+  __shared__ __align__(16) double GyB[kTile];
   __shared__ float Gx[XB * kTile];
-  __shared__ float Gy[2][kTile];
   __shared__ double red[2][NW];
   __shared__ int32_t s_item;
   // the wave index is uniform across a wave: readfirstlane lets the
-  // per-entry metadata come through scalar loads (lgkmcnt), so using it never
-  // waits on the in-order vector-memory counter of the tile prefetch
+  // per-entry metadata come through scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int unit = wave / WPU, sub = wave % WPU;
-  const int r0 = XB == 4 ? sub * 48 : (sub >> 1) * 48;
-  const int c0 = XB == 4 ? 0 : (sub & 1) * 48;
+  const int unit = wave >> 1, sub = wave & 1;
+  const int r0 = sub * 48;
   const double* hdr = reinterpret_cast<const double*>(ops);
+  const int xs = 2 * pw + 8;           // row stride (16-bit elements) in HBM and LDS
   const int tile_ch = kTile * xs / 8;  // 16-byte chunks per tile
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
   // this lane's contraction segments: x reads hi, hi, lo; y reads hi, lo,
@@ -187,6 +188,20 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     xoff[c] = seg < 3 ? (seg == 2 ? pw : 0) + off : 2 * pw;
     yoff[c] = seg < 3 ? (seg == 1 ? pw : 0) + off : 2 * pw;
   }
+  // copy of entry E's y tile and gaps into the LDS buffers (Y, G): wave w
+  // moves the 1 KB pieces w, w + NW, ...; the last wave also moves the gaps
+  auto issue = [&](int E, uint16_t* Y, double* G) {
+    const char* src = ops + entries[E].off_R;
+    for (int g = wave; g * 64 < tile_ch; g += NW) {
+      const int c = g * 64 + lane;
+      if (c < tile_ch)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 16 * (int64_t)c),
+                                         (lds_void_t*)(Y + g * 512), 16, 0, 0);
+    }
+    if (wave == NW - 1 && lane < kTile / 2)
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gap + entries[E].off_gap + 2 * lane),
+                                       (lds_void_t*)(G), 16, 0, 0);
+  };
   for (;;) {
     if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
@@ -195,6 +210,7 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
     if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
     if (ne == 0) continue;  // an item emptied by a pair mask
+    issue(e0, YsA, GyA);
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
     const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
@@ -218,33 +234,12 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
       const int f = xblocks[xbid].f[u];
       Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
     }
-    u16x8 pf[NPF];
-    double pg = 0.0;  // converted when stored, so the prefetch is not waited on early
-#define FEF_ISSUE(E)                                                                            \
-  {                                                                                             \
-    const u16x8* R_ = reinterpret_cast<const u16x8*>(ops + entries[E].off_R);                   \
-    _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
-      const int c_ = threadIdx.x + NT * k_;                                                     \
-      pf[k_] = R_[c_ < tile_ch ? c_ : tile_ch - 1];                                             \
-    }                                                                                           \
-    pg = gap[entries[E].off_gap + (threadIdx.x < kTile ? threadIdx.x : kTile - 1)];            \
-  }
-#define FEF_STORE(B)                                                                            \
-  {                                                                                             \
-    u16x8* d_ = reinterpret_cast<u16x8*>(Ys + (B) * kTile * xs);                                \
-    _Pragma("unroll") for (int k_ = 0; k_ < NPF; ++k_) {                                        \
-      const int c_ = threadIdx.x + NT * k_;                                                     \
-      if (c_ < tile_ch) d_[c_] = pf[k_];                                                        \
-    }                                                                                           \
-    if (threadIdx.x < kTile) Gy[B][threadIdx.x] = (float)pg;                                    \
-  }
-    FEF_ISSUE(e0)
-    FEF_STORE(0)
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int end = e0 + ne;
-    for (int e = e0; e < end; ++e) {
-      const int cur = (e - e0) & 1;
-      // this entry's metadata (scalar loads) before the next tile's prefetch
+    // one entry on buffer (Yc, Gc) while entry e + 1 is copied into (Yn, Gn)
+    auto entry = [&](int e, int cur, const uint16_t* Yc, const double* Gc, uint16_t* Yn,
+                     double* Gn) {
       const int slot = entries[e].slot[unit];
       double pscale = 0.0;
       if (sub == 0 && slot >= 0) {
@@ -252,13 +247,12 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
         const double sc = sx * hdr[2 * entries[e].y + 1];
         pscale = 4.0 * s * s * sc * sc;
       }
-      if (e + 1 < end) FEF_ISSUE(e + 1)
+      if (e + 1 < end) issue(e + 1, Yn, Gn);
       double mine = 0.0;
       if (slot >= 0) {
-        const uint16_t* Yb = Ys + cur * kTile * xs + (c0 + li) * xs;
+        const uint16_t* Yb = Yc + li * xs;
         // the wave's TJ column tiles in passes of TJP, so that TI x TJP
         // independent accumulators stay live over the whole contraction
-        constexpr int TJP = TJ < 3 ? TJ : 3;
         double part = 0.0;
 #pragma unroll
         for (int jh = 0; jh < TJ / TJP; ++jh) {
@@ -278,29 +272,29 @@ __global__ __launch_bounds__(512) void pair_split_kernel(
 #pragma unroll
               for (int j = 0; j < TJP; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
           }
-          part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0,
-                                             Gy[cur] + c0 + 16 * jh * TJP, lane);
+          part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0, Gc + 16 * jh * TJP,
+                                             lane);
         }
         mine = wave_sum(part);
       }
       if (lane == 0) red[cur][wave] = mine;
-      if (e + 1 < end) FEF_STORE(cur ^ 1)
+      // the copy into the next buffer has landed (this wave's part), and
+      // after the barrier every wave's part has
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (sub == 0 && lane == 0 && slot >= 0) {
-        double t = 0.0;
-        for (int q = 0; q < WPU; ++q) t += red[cur][unit * WPU + q];
-        partial[slot] = pscale * t;
-      }
+      if (sub == 0 && lane == 0 && slot >= 0)
+        partial[slot] = pscale * (red[cur][wave] + red[cur][wave + 1]);
+    };
+    for (int e = e0; e < end; e += 2) {
+      entry(e, 0, YsA, GyA, YsB, GyB);
+      if (e + 1 < end) entry(e + 1, 1, YsB, GyB, YsA, GyA);
     }
-#undef FEF_ISSUE
-#undef FEF_STORE
   }
 }
 
-size_t split_lds_bytes(int pw) { return (size_t)2 * kTile * (2 * pw + 8) * 2; }
 
 template <bool F16, int XB>
-static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds, hipStream_t st,
+static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, hipStream_t st,
                              const char* o, int prec, int pw, const double* gap,
                              const Entry* entries, const WorkItem* items, double* partial,
                              int32_t* head) {
@@ -308,7 +302,7 @@ static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds
   switch (nch) {
 #define FEF_NCH(N)                                                                                \
   case N:                                                                                         \
-    hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(512), lds, st, p.d_frag,       \
+    hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(128 * XB), 0, st, p.d_frag,    \
                        p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,                      \
                        (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);          \
     break;
@@ -319,19 +313,21 @@ static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, size_t lds
 
 hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
                               fef_prec prec, const Entry* entries, const WorkItem* items,
-                              double* partial, int32_t* head, int grid, hipStream_t st) {
+                              double* partial, int32_t* head, int ncu, hipStream_t st) {
   const char* o = static_cast<const char*>(ops);
   const int pw = p.geom[prec].pw, nch = p.geom[prec].kpad / 32;
   const int xb = p.tiles[prec].xb;
-  if (pw > 80 || nch < 1 || nch > 8) return hipErrorInvalidValue;
-  const size_t lds = split_lds_bytes(pw);
-  const dim3 g(grid);
+  if (pw > 80 || pw % 8 != 0 || nch < 1 || nch > 8) return hipErrorInvalidValue;
+  if ((p.ops_header & 15) != 0) return hipErrorInvalidValue;  // 16-byte copies
+  // persistent grid: one workgroup per CU (XB = 4) or two (XB = 2)
+  const int64_t want = (int64_t)ncu * (xb == 2 ? 2 : 1);
+  const dim3 g((unsigned)std::min<int64_t>(want, std::max<int64_t>(p.tiles[prec].nitems, 1)));
   if (prec == FEF_FP16X2) {
-    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_nch<true, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_nch<true, 2>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else if (prec == FEF_BF16X2) {
-    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_nch<false, 2>(p, nch, g, lds, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_nch<false, 2>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else {
     return hipErrorInvalidValue;
   }
