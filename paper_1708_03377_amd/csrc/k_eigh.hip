@@ -343,8 +343,11 @@ __device__ inline double bperm_d(int byte_addr, double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Bounded to two waves per SIMD (at most 256 registers): the 4000-matrix
+// batches then fit on the chip at once, and the two waves of a SIMD hide
+// each other's latency in the round's dependent chain.
 template <int M>
-__global__ __launch_bounds__(64) void eigh_wave_kernel(
+__global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list, int32_t count,
     const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
     double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
@@ -455,12 +458,10 @@ __global__ __launch_bounds__(64) void eigh_wave_kernel(
         v[2 * k] = ck * vp - sk * vq;
         v[2 * k + 1] = sk * vp + ck * vq;
       }
-      // rows of A with the partner lane
+      // rows of A with the partner lane: p <- c p - s q, q <- s p + c q
+      const double sg = odd ? s : -s;
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const double pj = dpp_swap_pair(a[j]);
-        a[j] = odd ? s * pj + c * a[j] : c * a[j] - s * pj;
-      }
+      for (int j = 0; j < M; ++j) a[j] = fma(sg, dpp_swap_pair(a[j]), c * a[j]);
       // relabel the slots
       double na[M], nv[M];
 #pragma unroll
