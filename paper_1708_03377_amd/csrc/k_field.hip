@@ -7,6 +7,8 @@
 //   J^x      = 2 sum_P B^x[P] phi^x_P ;  F~^x = F0^x + h~^x + J^x
 // Moments and J each stream B once (HBM bound); the neighbour sum gathers
 // P-vectors of the neighbours (L2 resident).
+#include <algorithm>
+
 #include "fef_internal.h"
 #include "fef_device.h"
 
@@ -107,21 +109,47 @@ __global__ __launch_bounds__(256) void field_kernel(
       y_off = frag[y].off_aux;
     }
     const int cnt = min(64, end - c0);
-#pragma unroll 8
-    for (int j = 0; j < cnt; ++j) {
-      const int cy = __builtin_amdgcn_readlane(y_cls, j);
-      const int lo = __builtin_amdgcn_readlane((int)y_off, j);
-      const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
-      const int64_t off = ((int64_t)hi << 32) | (uint32_t)lo;
-      const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
-                           0xffffffffLL;
-      const long long sh = __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
-      const double s = __longlong_as_double((sh << 32) | sb);
-      const double* dy = dmom + off;
-      if (cy == 0) {
-        if (lane < P0) e0 = fma(s, dy[lane], e0);
-        if (lane + 64 < P0) e1 = fma(s, dy[lane + 64], e1);
-      } else {
+    // class-0 neighbours, eight at a time: the weight of any other class is
+    // zeroed and its moments pointer parked at the pool start, so the loop
+    // has no branches and the eight neighbours' loads are in flight together
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+      double s8[8], v0[8], v1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, cnt - 1);
+        const bool use = j0 + u < cnt && __builtin_amdgcn_readlane(y_cls, j) == 0;
+        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
+        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
+        const int64_t off = use ? (((int64_t)hi << 32) | (uint32_t)lo) : 0;
+        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
+                             0xffffffffLL;
+        const long long sh =
+            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
+        s8[u] = use ? __longlong_as_double((sh << 32) | sb) : 0.0;
+        const double* dy = dmom + off;
+        v0[u] = lane < P0 ? dy[lane] : 0.0;
+        v1[u] = lane + 64 < P0 ? dy[lane + 64] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        e0 = fma(s8[u], v0[u], e0);
+        e1 = fma(s8[u], v1[u], e1);
+      }
+    }
+    // neighbours of other classes (rare): per-class sums in LDS
+    if (__any(k < end && y_cls != 0)) {
+      for (int j = 0; j < cnt; ++j) {
+        const int cy = __builtin_amdgcn_readlane(y_cls, j);
+        if (cy == 0) continue;
+        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
+        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
+        const int64_t off = ((int64_t)hi << 32) | (uint32_t)lo;
+        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
+                             0xffffffffLL;
+        const long long sh =
+            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
+        const double s = __longlong_as_double((sh << 32) | sb);
+        const double* dy = dmom + off;
         const int base = naux_cls_off[cy], pc = __builtin_amdgcn_readlane(y_naux, j);
         for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
       }
@@ -142,8 +170,17 @@ __global__ __launch_bounds__(256) void field_kernel(
       const double* ec = part + naux_cls_off[c];
       if (c == 0 && cx == 0) {
         // G_{0,0} is symmetric: read it by columns, so that consecutive
-        // threads (rows p) load consecutive addresses
-        for (int q = 0; q < pc; ++q) acc = fma(G[(int64_t)q * P0 + p], ec[q], acc);
+        // threads (rows p) load consecutive addresses; eight columns' loads
+        // in flight at a time
+        int q = 0;
+        for (; q + 8 <= pc; q += 8) {
+          double g8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) g8[u] = G[(int64_t)(q + u) * P0 + p];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = fma(g8[u], ec[q + u], acc);
+        }
+        for (; q < pc; ++q) acc = fma(G[(int64_t)q * P0 + p], ec[q], acc);
       } else if (c == 0) {
         const double* g = G + off_G[cx];  // G_{cx,0}: [P_cx][P0]
         for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)p * P0 + q], ec[q], acc);
@@ -234,8 +271,11 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
 }
 
 // d^x_Q = sum_k Bp[Q][k] Dw[k] from the packed slices and the weighted
-// packed density (each wave four Q, sixteen Q per block; 16-byte loads when
-// the triangle length and the offsets are even).
+// packed density.  Each wave takes kMomQW consecutive Q (four waves per
+// block); with 16-byte loads and triangles of at most 384 numbers (up to 27
+// basis functions) the k loop is unrolled, so that all of a wave's loads are
+// in flight together.
+constexpr int kMomQW = 8;
 __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
                                                              const int64_t* __restrict__ off_Bp,
                                                              const int64_t* __restrict__ off_tri,
@@ -243,35 +283,44 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
                                                              const double* __restrict__ Dw,
                                                              double* __restrict__ dmom) {
   const FragInfo fi = frag[blockIdx.x];
-  const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQ;
+  const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQW;
   if (q0 >= fi.naux) return;
   const int lane = threadIdx.x & 63;
-  const int nq = min(kMomQ, fi.naux - q0);
+  const int nq = min(kMomQW, fi.naux - q0);
   const int n = fi.nbf, nt = n * (n + 1) / 2;
   const int64_t ob = off_Bp[blockIdx.x] + (int64_t)q0 * nt, od = off_tri[blockIdx.x];
   const double* b = Bp + ob;
   const double* d = Dw + od;
-  double acc[kMomQ] = {0.0, 0.0, 0.0, 0.0};
-  if ((nt & 1) == 0 && (ob & 1) == 0 && (od & 1) == 0) {
-    for (int k = 2 * lane; k < nt; k += 128) {
-      const double2 dv = *reinterpret_cast<const double2*>(d + k);
+  double acc[kMomQW];
 #pragma unroll
-      for (int q = 0; q < kMomQ; ++q)
-        if (q < nq) {
-          const double2 bv = *reinterpret_cast<const double2*>(b + (int64_t)q * nt + k);
-          acc[q] = fma(bv.y, dv.y, fma(bv.x, dv.x, acc[q]));
-        }
+  for (int q = 0; q < kMomQW; ++q) acc[q] = 0.0;
+  if ((nt & 1) == 0 && (ob & 1) == 0 && (od & 1) == 0 && nt <= 384) {
+    double2 dv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = 2 * lane + 128 * c;
+      dv[c] = k < nt ? *reinterpret_cast<const double2*>(d + k) : double2{0.0, 0.0};
     }
+#pragma unroll
+    for (int q = 0; q < kMomQW; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int k = 2 * lane + 128 * c;
+        if (q < nq && k < nt) {
+          const double2 bv = *reinterpret_cast<const double2*>(b + (int64_t)q * nt + k);
+          acc[q] = fma(bv.y, dv[c].y, fma(bv.x, dv[c].x, acc[q]));
+        }
+      }
   } else {
     for (int k = lane; k < nt; k += 64) {
-      const double dv = d[k];
+      const double dk = d[k];
 #pragma unroll
-      for (int q = 0; q < kMomQ; ++q)
-        if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dv, acc[q]);
+      for (int q = 0; q < kMomQW; ++q)
+        if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dk, acc[q]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < kMomQ; ++q) {
+  for (int q = 0; q < kMomQW; ++q) {
     const double t = wave_sum(acc[q]);
     if (lane == 0 && q < nq) dmom[fi.off_aux + q0 + q] = t;
   }
@@ -279,7 +328,7 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
 
 // out = F0 + h~ + 2 sum_P B[P] phi_P from the packed slices, both mirror
 // elements written.
-__global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __restrict__ frag,
+__global__ __launch_bounds__(1024) void jbuild_packed_kernel(const FragInfo* __restrict__ frag,
                                                             const int64_t* __restrict__ off_Bp,
                                                             const double* __restrict__ Bp,
                                                             const double* __restrict__ phi,
@@ -292,9 +341,16 @@ __global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __re
   if (k >= nt) return;
   const double* b = Bp + off_Bp[blockIdx.x] + k;
   const double* ph = phi + fi.off_aux;
-  double acc = 0.0;
-#pragma unroll 8
-  for (int P = 0; P < fi.naux; ++P) acc = fma(b[(int64_t)P * nt], ph[P], acc);
+  // four independent partial sums (P mod 4), so that loads of several
+  // slices are in flight at once
+  double a4[4] = {0.0, 0.0, 0.0, 0.0};
+  int P = 0;
+#pragma unroll 4
+  for (; P + 4 <= fi.naux; P += 4)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a4[u] = fma(b[(int64_t)(P + u) * nt], ph[P + u], a4[u]);
+  for (; P < fi.naux; ++P) a4[0] = fma(b[(int64_t)P * nt], ph[P], a4[0]);
+  const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
   int mu, nu;
   tri_row_col(k, n, mu, nu);
   const double j2 = 2.0 * acc;
@@ -318,14 +374,16 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st) {
   hipLaunchKernelGGL(moments_packed_kernel,
-                     dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)), dim3(256), 0, st,
+                     dim3(p.nfrag, (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW)), dim3(256), 0, st,
                      p.d_frag, p.d_off_Bp, p.d_off_tri, Bp, Dw, ws_d);
   const int etot = p.naux_cls_off.back();
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                      p.d_naux_cls_off, ws_d, ws_phi);
+  // one block per fragment triangle when it fits 1024 threads (water: 320)
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
-  hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + 255) / 256), dim3(256), 0, st,
+  const int jt = std::min(1024, (ntmax + 63) / 64 * 64);
+  hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + jt - 1) / jt), dim3(jt), 0, st,
                      p.d_frag, p.d_off_Bp, Bp, ws_phi, F0, htilde, out);
   return hipGetLastError();
 }
