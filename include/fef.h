@@ -134,8 +134,9 @@ fef_status fef_plan_query(fef_plan plan, fef_query what, fef_prec prec,
 /* Pair-kernel tiling of mode `prec` (the work decomposition; results agree
  * across tilings up to the rounding order of the in-tile sums, and are
  * bitwise reproducible for a fixed tiling).
- *   xb : x-side row tiles held by one workgroup (FP64/FP32: 1; split modes:
- *        2 or 4), each y tile streamed through the workgroup serves all.
+ *   xb : x-side row tiles held by one workgroup (FP64/FP32: 1 or 2; split
+ *        modes: 2 or 4), each y tile streamed through the workgroup serves
+ *        all.
  *   yc : y tiles per work item of the persistent queue (1..4096).
  * Rebuilds device tables (allocates): call outside graph capture, with no
  * pair-energy call of this plan in flight.  The autotuner uses this. */

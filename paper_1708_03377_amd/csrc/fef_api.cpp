@@ -159,7 +159,6 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   for (int k = 0; k < FEF_NPREC; ++k) p->geom[k] = geom_of(k, p->P0);
   configure_split_kernels(p->geom[FEF_BF16X2].pw);
   (void)compute_units();
-  configure_plain_kernels(p->geom[FEF_F64].kpad, p->geom[FEF_F32].kpad);
 
   // ---- fragment table -----------------------------------------------------
   p->frag.resize(d->nfrag);
@@ -395,7 +394,7 @@ fef_status fef_plan_set_tiles(fef_plan p, fef_prec prec, int32_t xb, int32_t yc)
   if (!p) return FEF_E_ARG;
   if (!valid_prec(prec)) return FEF_E_PREC;
   const bool plain = prec == FEF_F64 || prec == FEF_F32;
-  if (plain ? xb != 1 : (xb != 2 && xb != 4)) return FEF_E_UNSUPPORTED;
+  if (plain ? (xb != 1 && xb != 2) : (xb != 2 && xb != 4)) return FEF_E_UNSUPPORTED;
   if (yc < 1 || yc > 4096) return FEF_E_ARG;
   return hip_status(build_tiles(*p, prec, xb, yc));
 }

@@ -108,7 +108,8 @@ fef_status fef_autotune(fef_plan p, const void* ops, const double* eps, fef_prec
   std::vector<std::pair<int, int>> cand;
   const int ycs[] = {8, 16, 32, 64};
   if (plain) {
-    for (int yc : ycs) cand.push_back({1, yc});
+    for (int xb : {1, 2})
+      for (int yc : ycs) cand.push_back({xb, yc});
   } else {
     for (int xb : {2, 4})
       for (int yc : ycs) cand.push_back({xb, yc});

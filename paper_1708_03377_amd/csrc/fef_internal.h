@@ -225,7 +225,6 @@ int compute_units();
 
 // One-time kernel attributes (dynamic LDS above 64 KB).
 void configure_split_kernels(int pw);
-void configure_plain_kernels(int kpad64, int kpad32);
 
 // Workspace sizes (bytes).
 int64_t half_ws_bytes(const fef_plan_s& p, fef_prec prec);

@@ -32,35 +32,59 @@ struct Mfma<float> {
   }
 };
 
-// Persistent FP64 / FP32 pair kernel.  A workgroup pulls work items from a
-// global queue (LPT order).  An item is one x unit (fragment x, row tile mt)
-// and a run of y tiles: the x tile (kpad x 96, k-major) sits in LDS for the
-// whole item; each y tile is staged in LDS too, the next one being fetched
-// into registers while the current one is contracted by four waves, each a
-// 48x48 quadrant of V (3x3 MFMA tiles).  Orbital-energy gaps of both sides
-// are staged with their tiles.
-template <typename T, int KS>
-__global__ __launch_bounds__(256) void pair_plain_kernel(
+// Persistent FP64 / FP32 pair kernel.  A workgroup pulls work items from the
+// queue groups (LPT order inside each).  An item is XB x units (fragment x,
+// row tile mt) and a run of y tiles.  Four waves serve a unit, each a 48x48
+// quadrant of V (3x3 MFMA tiles); a wave keeps its x rows (the MFMA A
+// operand of every k step) in registers for the whole item.  Each y tile
+// ([kpad][96], k-major) and its gaps are copied from global memory straight
+// into one of two LDS buffers (global_load_lds, 16 bytes per lane) while the
+// other buffer is contracted; the buffers are separate LDS arrays, so reads
+// of the current one never wait for the copy into the next.  With two units
+// a workgroup has eight waves, two per SIMD.
+constexpr int kPadMax = 80;
+typedef __attribute__((address_space(3))) void plain_lds_t;
+
+template <typename T, int KS, int XB>
+__global__ __launch_bounds__(256 * XB) void pair_plain_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
     int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops, int prec, int kpad,
     const double* __restrict__ gap, double* __restrict__ partial) {
   typedef typename Mfma<T>::acc_t acc_t;
-  typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-  constexpr int kVec = 16 / sizeof(T);        // elements per 16-byte chunk
-  constexpr int kRowCh = kTile / kVec;        // chunks per k-row of a tile
-  constexpr int NPF = (80 * kRowCh + 255) / 256;  // staging chunks per thread (kpad <= 80)
-  extern __shared__ char smem[];
-  T* Xs = reinterpret_cast<T*>(smem);          // [kpad][kTile]
-  T* Ys = Xs + kpad * kTile;                   // [kpad][kTile]
-  __shared__ double Gx[kTile], Gy[kTile];
-  __shared__ double red[4];
+  static_assert(4 * KS <= kPadMax, "k steps");
+  constexpr int NT = 256 * XB, NW = 4 * XB;
+  constexpr int kRowCh = kTile * (int)sizeof(T) / 16;  // 16-byte chunks per k row of a tile
+  __shared__ __align__(16) T YsA[kPadMax * kTile];
+  __shared__ __align__(16) T YsB[kPadMax * kTile];
+  __shared__ __align__(16) double GyA[kTile];
+  __shared__ __align__(16) double GyB[kTile];
+  __shared__ double Gx[XB * kTile];
+  __shared__ double red[2][NW];
   __shared__ int32_t s_item;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = (wave >> 1) * 48, c0 = (wave & 1) * 48;
-  const int tot = kpad * kRowCh;
+  const int unit = wave >> 2, sub = wave & 3;
+  const int r0 = (sub >> 1) * 48, c0 = (sub & 1) * 48;
+  const int tile_ch = kpad * kRowCh;
+  // copy of entry E's y tile ([kpad][96] of a [kpad][ld_y] operand) and gaps
+  auto issue = [&](int E, T* Y, double* G) {
+    const int64_t yld = entries[E].ld_y;
+    const char* src = ops + entries[E].off_R;
+    for (int g = wave; g * 64 < tile_ch; g += NW) {
+      const int c = g * 64 + lane;
+      if (c < tile_ch) {
+        const int k = c / kRowCh, q = c - (c / kRowCh) * kRowCh;
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void*>(src + ((int64_t)k * yld * sizeof(T) + 16 * q)),
+            (plain_lds_t*)(Y + g * 64 * (16 / (int)sizeof(T))), 16, 0, 0);
+      }
+    }
+    if (wave == NW - 1 && lane < kTile / 2)
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gap + entries[E].off_gap + 2 * lane),
+                                       (plain_lds_t*)(G), 16, 0, 0);
+  };
   for (;;) {
     if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
@@ -69,76 +93,71 @@ __global__ __launch_bounds__(256) void pair_plain_kernel(
     if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
     if (ne == 0) continue;  // an item emptied by a pair mask
-    const int fxi = xblocks[xbid].f[0];
-    const int mt = xblocks[xbid].mt[0];
-    {
+    issue(e0, YsA, GyA);
+    const int fxi = xblocks[xbid].f[unit];
+    const int mt = xblocks[xbid].mt[unit];
+    // x rows r0 + 16 i + li at k = 4 s + lk, all k steps
+    T xa[3][KS];
+    if (fxi >= 0) {
       const int64_t xld = frag[fxi].ld;
-      const T* L = reinterpret_cast<const T*>(ops + frag[fxi].off_L[prec]) + mt * kTile;
-      for (int c = threadIdx.x; c < tot; c += 256) {
-        const int k = c / kRowCh, q = c - (c / kRowCh) * kRowCh;
-        *reinterpret_cast<i32x4*>(Xs + k * kTile + q * kVec) =
-            *reinterpret_cast<const i32x4*>(L + (int64_t)k * xld + q * kVec);
-      }
-      if (threadIdx.x < kTile) Gx[threadIdx.x] = gap[frag[fxi].off_gap + mt * kTile + threadIdx.x];
+      const T* L = reinterpret_cast<const T*>(ops + frag[fxi].off_L[prec]) + mt * kTile + r0 + li;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          xa[i][s] = 4 * s + lk < kpad ? L[(int64_t)(4 * s + lk) * xld + 16 * i] : (T)0;
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xa[i][s] = (T)0;
     }
-    i32x4 pf[NPF];
-    double pg = 0.0;
-    auto issue = [&](int e) {
-      const int64_t yld = entries[e].ld_y;
-      const T* R = reinterpret_cast<const T*>(ops + entries[e].off_R);
+    for (int t = threadIdx.x; t < XB * kTile; t += NT) {
+      const int u = t / kTile, m = t - (t / kTile) * kTile;
+      const int f = xblocks[xbid].f[u];
+      Gx[t] = f >= 0 ? gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int end = e0 + ne;
+    auto entry = [&](int e, int cur, const T* Yc, const double* Gc, T* Yn, double* Gn) {
+      const int slot = entries[e].slot[unit];
+      const double s = entries[e].s[unit];
+      if (e + 1 < end) issue(e + 1, Yn, Gn);
+      double mine = 0.0;
+      if (slot >= 0) {
+        acc_t acc[3][3];
 #pragma unroll
-      for (int k = 0; k < NPF; ++k) {
-        const int c = threadIdx.x + 256 * k;
-        if (c < tot) {
-          const int kk = c / kRowCh, q = c - (c / kRowCh) * kRowCh;
-          pf[k] = *reinterpret_cast<const i32x4*>(R + (int64_t)kk * yld + q * kVec);
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        const T* yr = Yc + lk * kTile + c0 + li;
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+          T b[3];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) b[j] = yr[4 * st * kTile + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[i][j] = Mfma<T>::mma(xa[i][st], b[j], acc[i][j]);
         }
+        mine = wave_sum(weighted_tiles<sizeof(T) == 8, 3, 3>(acc, Gx + unit * kTile + r0,
+                                                              Gc + c0, lane, 1.0));
       }
-      if (threadIdx.x < kTile) pg = gap[entries[e].off_gap + threadIdx.x];
-    };
-    issue(e0);
-    for (int e = e0; e < e0 + ne; ++e) {
-      __syncthreads();  // x tile stored / previous y tile consumed
-#pragma unroll
-      for (int k = 0; k < NPF; ++k) {
-        const int c = threadIdx.x + 256 * k;
-        if (c < tot) *reinterpret_cast<i32x4*>(Ys + c * kVec) = pf[k];
-      }
-      if (threadIdx.x < kTile) Gy[threadIdx.x] = pg;
+      if (lane == 0) red[cur][wave] = mine;
+      // this wave's part of the next copy has landed; after the barrier,
+      // every wave's part has
+      __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (e + 1 < e0 + ne) issue(e + 1);
-      const int slot = entries[e].slot[0];
-      acc_t acc[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-      // KS > 0: the contraction loop is fully unrolled so the accumulators
-      // stay in the MFMA registers across steps
-#define FEF_KSTEP(K0)                                                              \
-  {                                                                                \
-    const T* xr = Xs + ((K0) + lk) * kTile + r0 + li;                              \
-    const T* yr = Ys + ((K0) + lk) * kTile + c0 + li;                              \
-    T a[3], b[3];                                                                  \
-    _Pragma("unroll") for (int i = 0; i < 3; ++i) a[i] = xr[16 * i];                \
-    _Pragma("unroll") for (int j = 0; j < 3; ++j) b[j] = yr[16 * j];                \
-    _Pragma("unroll") for (int i = 0; i < 3; ++i)                                   \
-      _Pragma("unroll") for (int j = 0; j < 3; ++j)                                 \
-        acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);                            \
-  }
-      if constexpr (KS > 0) {
-#pragma unroll
-        for (int st = 0; st < KS; ++st) FEF_KSTEP(4 * st)
-      } else {
-        for (int k = 0; k < kpad; k += 4) FEF_KSTEP(k)
-      }
-#undef FEF_KSTEP
-      const double sum = weighted_tiles<sizeof(T) == 8, 3, 3>(acc, Gx + r0, Gy + c0, lane, 1.0);
-      const double total = block_sum(sum, red);
-      if (threadIdx.x == 0) {
-        const double s = entries[e].s[0];
-        partial[slot] = 4.0 * s * s * total;
-      }
+      if (sub == 0 && lane == 0 && slot >= 0)
+        partial[slot] = 4.0 * s * s *
+                        ((red[cur][wave] + red[cur][wave + 1]) +
+                         (red[cur][wave + 2] + red[cur][wave + 3]));
+    };
+    for (int e = e0; e < end; e += 2) {
+      entry(e, 0, YsA, GyA, YsB, GyB);
+      if (e + 1 < end) entry(e + 1, 1, YsB, GyB, YsA, GyA);
     }
   }
 }
@@ -193,21 +212,6 @@ __global__ __launch_bounds__(256) void gaps_kernel(const FragInfo* __restrict__ 
     gap[fi.off_gap + m] = g;
   }
   if (bad) atomicOr(flags, FEF_FLAG_GAP);
-}
-
-void configure_plain_kernels(int kpad64, int kpad32) {
-  const int need64 = 2 * kpad64 * kTile * (int)sizeof(double);
-  const int need32 = 2 * kpad32 * kTile * (int)sizeof(float);
-  if (need64 > 65536) {
-    (void)hipFuncSetAttribute((const void*)pair_plain_kernel<double, 18>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, need64);
-    (void)hipFuncSetAttribute((const void*)pair_plain_kernel<double, 0>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, need64);
-  }
-  if (need32 > 65536)
-    (void)hipFuncSetAttribute((const void*)pair_plain_kernel<float, 0>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, need32);
-  (void)hipGetLastError();
 }
 
 // E2_pair[p] = sum of the pair's tile partials, in slot order; with a mask,
@@ -300,19 +304,21 @@ hipError_t launch_pair_energies(const fef_plan_s& p, const void* ops, const doub
       case FEF_F64:
       case FEF_F32: {
         const bool f64 = prec == FEF_F64;
-        const dim3 grid(persistent_grid(t.nitems, f64 ? 1 : 2));
-        const size_t lds = 2 * (size_t)kpad * kTile * (f64 ? sizeof(double) : sizeof(float));
-#define FEF_PLAIN(T, KS)                                                                        \
-  hipLaunchKernelGGL((pair_plain_kernel<T, KS>), grid, dim3(256), lds, st, p.d_frag, p.d_pair,  \
-                     p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,             \
+        const int xbp = t.xb == 2 ? 2 : 1;
+        const dim3 grid(persistent_grid(t.nitems, f64 || xbp == 2 ? 1 : 2));
+#define FEF_PLAIN(T, KS, XB)                                                                    \
+  hipLaunchKernelGGL((pair_plain_kernel<T, KS, XB>), grid, dim3(256 * XB), 0, st, p.d_frag,    \
+                     p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,   \
                      head, t.d_grp_off, o, (int)prec, kpad, gap, partial)
+#define FEF_PLAIN_K(T, XB)                                                                      \
+  if (kpad == 72) FEF_PLAIN(T, 18, XB); else if (kpad == 8) FEF_PLAIN(T, 2, XB);                \
+  else FEF_PLAIN(T, kPadMax / 4, XB)
         if (f64) {
-          if (kpad == 72) FEF_PLAIN(double, 18); else if (kpad == 8) FEF_PLAIN(double, 2);
-          else FEF_PLAIN(double, 0);
+          if (xbp == 2) { FEF_PLAIN_K(double, 2); } else { FEF_PLAIN_K(double, 1); }
         } else {
-          if (kpad == 72) FEF_PLAIN(float, 18); else if (kpad == 8) FEF_PLAIN(float, 2);
-          else FEF_PLAIN(float, 0);
+          if (xbp == 2) { FEF_PLAIN_K(float, 2); } else { FEF_PLAIN_K(float, 1); }
         }
+#undef FEF_PLAIN_K
 #undef FEF_PLAIN
         break;
       }

@@ -186,7 +186,8 @@ def test_reduced_precision_config0(torch, prec, tol_pair):
     assert err <= tol_pair
 
 
-@pytest.mark.parametrize("prec,tiles", [("f64", [(1, 1), (1, 7)]), ("f32", [(1, 3)]),
+@pytest.mark.parametrize("prec,tiles", [("f64", [(1, 1), (1, 7), (2, 1), (2, 5)]),
+                                        ("f32", [(1, 3), (2, 2)]),
                                         ("bf16x2", [(2, 2), (2, 5), (4, 64)]),
                                         ("fp16x2", [(2, 1), (4, 3)])])
 def test_tilings_agree(torch, prec, tiles):
