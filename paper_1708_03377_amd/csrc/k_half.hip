@@ -92,25 +92,41 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     Bs[pp * kBld + ia] = (pp < P && ia < ov) ? bov[fi.off_bov + (int64_t)pp * ov + ia] : 0.0;
   }
   __syncthreads();
-  // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia tile),
-  // tile t = wave + 4 k; A = G^T read from the (L2-resident) coupling, B from LDS
+  // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia
+  // tile) in q-major order, eight consecutive tiles per wave, so that a wave
+  // meets at most two q tiles.  The A operands (G^T, from the L2-resident
+  // coupling) of those two q tiles for every k step are loaded into
+  // registers first; B comes from LDS.
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const double* g = G + off_G[fi.cls];  // [P][P0]
-  const int QT = (P0 + 15) >> 4, NT = QT * (kTile / 16);
-  constexpr int kTilesPerWave = (5 * (kTile / 16) + 3) / 4;
+  constexpr int kIT = kTile / 16;
+  const int QT = (P0 + 15) >> 4, NT = QT * kIT;
+  constexpr int kTilesPerWave = (5 * kIT + 3) / 4;  // 8 (P0 <= 80)
+  constexpr int kSteps = kSmallP / 4;               // 20
+  const int t0 = wave * kTilesPerWave;
+  const int qa = t0 / kIT;  // first q tile of this wave; the other is qa + 1
+  double ga[2][kSteps];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int ks = 0; ks < kSteps; ++ks) {
+      const int pp = 4 * ks + lk, q = 16 * (qa + h) + li;
+      ga[h][ks] = (pp < P && q < P0) ? g[(int64_t)pp * P0 + q] : 0.0;
+    }
   d4 acc[kTilesPerWave];
 #pragma unroll
   for (int k = 0; k < kTilesPerWave; ++k) acc[k] = d4{0, 0, 0, 0};
-  for (int ks = 0; ks < P4 / 4; ++ks) {
+#pragma unroll
+  for (int ks = 0; ks < kSteps; ++ks) {
+    if (4 * ks >= P4) break;
     const int pp = 4 * ks + lk;
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
-      const int t = wave + 4 * k;
-      if (t < NT) {
-        const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
-        const int q = 16 * qt + li;
-        const double av = (pp < P && q < P0) ? g[(int64_t)pp * P0 + q] : 0.0;
+      const int tt = t0 + k;
+      if (tt < NT) {
+        const int qt = tt / kIT, it = tt - qt * kIT;
+        const double av = qt == qa ? ga[0][ks] : ga[1][ks];
         const double bv = Bs[pp * kBld + 16 * it + li];
         acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
       }
@@ -120,7 +136,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
   double wmax = 0.0, bmax = 0.0;
 #pragma unroll
   for (int k = 0; k < kTilesPerWave; ++k) {
-    const int t = wave + 4 * k;
+    const int t = t0 + k;
     if (t < NT) {
       const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
 #pragma unroll
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     // [kpad][ld]: values, then zeros in the padding
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
-      const int t = wave + 4 * k;
+      const int t = t0 + k;
       if (t < NT) {
         const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
 #pragma unroll
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const int wld = P0 + 1;
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
-      const int t = wave + 4 * k;
+      const int t = t0 + k;
       if (t < NT) {
         const int qt = t / (kTile / 16), it = t - qt * (kTile / 16);
 #pragma unroll
