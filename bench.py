@@ -15,7 +15,13 @@ each mode's errors are reported beside it.
 The roofline entry covers the pair contraction of the headline mode: the
 algorithmic flops of one launch (2 ov_x ov_y P0 per pair, the products of the
 exact method, not the three split products) divided by the launch's average
-duration, timed with HIP events on the stream the library launches on.
+duration, timed with HIP events on the stream the library launches on.  The
+flops the MFMA units actually issue (whole 96-row tiles, padded contraction
+length, the three split products) are reported beside it (issued_frac).
+
+Each mode also reports the half transform + pair energies unit on the final
+orbitals on its own: 25 event-timed repetitions, the first 5 discarded,
+median / min / max.
 
 Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
@@ -64,6 +70,20 @@ def pair_flops(sysm) -> float:
     return float(np.sum(2.0 * ov[sysm.pair_x] * ov[sysm.pair_y] * p0))
 
 
+def pair_issued_flops(sysm, mode: str) -> float:
+    """Flops the MFMA units issue for one launch: whole 96-row tiles on both
+    sides and the padded contraction length (split modes: the three split
+    products, K = 3 round_up(P0, 8) rounded up to a multiple of 32)."""
+    ov = sysm.nocc.astype(np.int64) * (sysm.nbf - sysm.nocc).astype(np.int64)
+    ld = ((ov + 95) // 96) * 96
+    p0 = int(sysm.naux_class[0])
+    if mode in ("f64", "f32"):
+        k = ((p0 + 3) // 4) * 4
+    else:
+        k = ((3 * ((p0 + 7) // 8) * 8 + 31) // 32) * 32
+    return float(np.sum(2.0 * ld[sysm.pair_x] * ld[sysm.pair_y] * k))
+
+
 def pair_operand_bytes(ctx, prec: int) -> int:
     """Bytes of the packed operand pool one launch reads at least once."""
     from paper_1708_03377_amd import _fef
@@ -106,11 +126,22 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
     spent; scaled to one full step (niter SCF steps + every pair)."""
     from oracle import fef as ofef
     threads = 1
+    blas = "unknown"
     try:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
         threads = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = ", ".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info
+                                 if i.get("user_api") == "blas"})) or blas
     except ImportError:
+        pass
+    cpu_model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu_model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
         pass
     t0 = time.perf_counter()
     C, e, _, _, _ = ofef.scf_step(sysm, sysm.C.copy(), sysm.eps.copy())
@@ -128,7 +159,8 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
         done += n
     step_s = niter * t_scf + sysm.npair * (t_pairs / done)
     return {"value": sysm.npair / step_s, "unit": "pairs/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model, "blas": blas,
+            "affinity_cpus": len(os.sched_getaffinity(0)),
             "sample": f"1 FP64 SCF step over all {sysm.nfrag} fragments ({t_scf:.2f} s) and "
                       f"{done} random pairs ({t_pairs:.2f} s), scaled to {niter} SCF steps + "
                       f"all {sysm.npair} pairs"}
@@ -198,6 +230,16 @@ def main():
             b.record(st)
         torch.cuda.synchronize()
         pair_ms = float(np.mean([a.elapsed_time(b) for a, b in pe]))
+        # the half transform + pair energies unit on the current orbitals,
+        # each repetition event-timed: median, min and max of 20 after 5
+        hp = [(ev(), ev()) for _ in range(25)]
+        for a, b in hp:
+            a.record(st)
+            ctx.half_transform(prec)
+            ctx.pair_energies(prec)
+            b.record(st)
+        torch.cuda.synchronize()
+        unit = [a.elapsed_time(b) for a, b in hp][5:]
         # the timed steps: graph replays of the whole pass
         g = ctx.graph(niter, prec, from_start=True)
         for _ in range(args.warmup):
@@ -214,7 +256,7 @@ def main():
         gpu_ms = float(np.mean([a.elapsed_time(b) for a, b in ge]))
         results[name] = {
             "ms_per_step": 1e3 * wall / args.steps, "gpu_ms_per_step": gpu_ms,
-            "stage_ms": stage, "pair_ms": pair_ms, "tiles": (xb, yc),
+            "stage_ms": stage, "pair_ms": pair_ms, "tiles": (xb, yc), "unit_ms": unit,
             "E_total": float(ctx.E2_total.cpu()[0]), "flags": int(ctx.flags.cpu()[0]),
             "E2": ctx.E2_pair[:ctx.npair].cpu().numpy().copy()}
         del g
@@ -233,6 +275,11 @@ def main():
             "scf_ms": round(r["stage_ms"][0], 4), "half_ms": round(r["stage_ms"][1], 4),
             "pair_ms": round(r["pair_ms"], 4),
             "pair_tflops": pair_flops(sysm) / (r["pair_ms"] / 1e3) / 1e12,
+            "half_plus_pair": {"median_ms": round(float(np.median(r["unit_ms"])), 4),
+                               "min_ms": round(float(np.min(r["unit_ms"])), 4),
+                               "max_ms": round(float(np.max(r["unit_ms"])), 4),
+                               "reps": len(r["unit_ms"]), "warmup": 5,
+                               "pairs_per_s": sysm.npair / (float(np.median(r["unit_ms"])) / 1e3)},
             "tiles_xb_yc": list(r["tiles"]),
             "total_err_vs_f64": err_tot, "max_pair_err_vs_f64": err_pair,
             "E2_total": r["E_total"], "flags": r["flags"]}
@@ -258,6 +305,8 @@ def main():
                      "frac": achieved / peak,
                      "traffic": traffic_from_profiles(head, spec.name),
                      "algorithmic_flops_per_launch": flops,
+                     "issued_flops_per_launch": pair_issued_flops(sysm, head),
+                     "issued_frac": pair_issued_flops(sysm, head) / (h["pair_ms"] / 1e3) / peak,
                      "launch_ms": h["pair_ms"],
                      "operand_bytes": pair_operand_bytes(ctx, lib.PREC[head])},
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],
