@@ -188,6 +188,8 @@ hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, c
                            double* dmax, int32_t* flags, double* ws_eig, hipStream_t st);
 hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
                                     hipStream_t st);
+// every fragment has nbf <= 32 and P <= 80 (the fused field + J kernel applies)
+bool small_fragments(const fef_plan_s& p);
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st);

@@ -362,6 +362,153 @@ __global__ __launch_bounds__(1024) void jbuild_packed_kernel(const FragInfo* __r
   if (mu != nu) out[o2] = v2;
 }
 
+// Field and J in one kernel, one workgroup per fragment (every fragment
+// small enough that its packed triangle fits one workgroup): the field
+// gather of one fragment is latency-bound and its J build streams the
+// fragment's coefficients, so workgroups in different phases overlap, and
+// phi stays in LDS.
+__global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ nbr_ptr,
+    const int32_t* __restrict__ nbr_idx, const double* __restrict__ nbr_s,
+    const double* __restrict__ G, const int64_t* __restrict__ off_G, int P0, int nclass,
+    const int32_t* __restrict__ naux_cls_off, const double* __restrict__ dmom,
+    const int64_t* __restrict__ off_Bp, const double* __restrict__ Bp,
+    const double* __restrict__ F0, const double* __restrict__ htilde, double* __restrict__ out) {
+  extern __shared__ double part[];  // [NW][etot] per-wave partial e_c, then e; then phi^x
+  const int NW = blockDim.x >> 6;
+  const int x = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int etot = naux_cls_off[nclass];
+  for (int t = threadIdx.x; t < NW * etot; t += blockDim.x) part[t] = 0.0;
+  __syncthreads();
+  double* mine = part + wave * etot;
+  const int beg = nbr_ptr[x], end = nbr_ptr[x + 1];
+  double e0 = 0.0, e1 = 0.0;
+  for (int c0 = beg + 64 * wave; c0 < end; c0 += 64 * NW) {
+    const int k = c0 + lane;
+    int y_cls = 0, y_naux = 0;
+    int64_t y_off = 0;
+    double y_s = 0.0;
+    if (k < end) {
+      const int y = nbr_idx[k];
+      y_s = nbr_s[k];
+      y_cls = frag[y].cls;
+      y_naux = frag[y].naux;
+      y_off = frag[y].off_aux;
+    }
+    const int cnt = min(64, end - c0);
+    // class-0 neighbours, eight at a time: the weight of any other class is
+    // zeroed and its moments pointer parked at the pool start, so the loop
+    // has no branches and the eight neighbours' loads are in flight together
+    for (int j0 = 0; j0 < cnt; j0 += 8) {
+      double s8[8], v0[8], v1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = min(j0 + u, cnt - 1);
+        const bool use = j0 + u < cnt && __builtin_amdgcn_readlane(y_cls, j) == 0;
+        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
+        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
+        const int64_t off = use ? (((int64_t)hi << 32) | (uint32_t)lo) : 0;
+        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
+                             0xffffffffLL;
+        const long long sh =
+            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
+        s8[u] = use ? __longlong_as_double((sh << 32) | sb) : 0.0;
+        const double* dy = dmom + off;
+        v0[u] = lane < P0 ? dy[lane] : 0.0;
+        v1[u] = lane + 64 < P0 ? dy[lane + 64] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        e0 = fma(s8[u], v0[u], e0);
+        e1 = fma(s8[u], v1[u], e1);
+      }
+    }
+    // neighbours of other classes (rare): per-class sums in LDS
+    if (__any(k < end && y_cls != 0)) {
+      for (int j = 0; j < cnt; ++j) {
+        const int cy = __builtin_amdgcn_readlane(y_cls, j);
+        if (cy == 0) continue;
+        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
+        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
+        const int64_t off = ((int64_t)hi << 32) | (uint32_t)lo;
+        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
+                             0xffffffffLL;
+        const long long sh =
+            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
+        const double s = __longlong_as_double((sh << 32) | sb);
+        const double* dy = dmom + off;
+        const int base = naux_cls_off[cy], pc = __builtin_amdgcn_readlane(y_naux, j);
+        for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
+      }
+    }
+  }
+  if (lane < P0) mine[lane] += e0;
+  if (lane + 64 < P0) mine[lane + 64] += e1;
+  __syncthreads();
+  for (int q = threadIdx.x; q < etot; q += blockDim.x) {
+    double s = part[q];
+    for (int w = 1; w < NW; ++w) s += part[w * etot + q];
+    part[q] = s;
+  }
+  __syncthreads();
+  double* phis = part + NW * etot;
+  const FragInfo fx = frag[x];
+  const int cx = fx.cls;
+  for (int p = threadIdx.x; p < fx.naux; p += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < nclass; ++c) {
+      const int pc = naux_cls_off[c + 1] - naux_cls_off[c];
+      const double* ec = part + naux_cls_off[c];
+      if (c == 0 && cx == 0) {
+        // G_{0,0} is symmetric: read it by columns, so that consecutive
+        // threads (rows p) load consecutive addresses; eight columns' loads
+        // in flight at a time
+        int q = 0;
+        for (; q + 8 <= pc; q += 8) {
+          double g8[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) g8[u] = G[(int64_t)(q + u) * P0 + p];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc = fma(g8[u], ec[q + u], acc);
+        }
+        for (; q < pc; ++q) acc = fma(G[(int64_t)q * P0 + p], ec[q], acc);
+      } else if (c == 0) {
+        const double* g = G + off_G[cx];  // G_{cx,0}: [P_cx][P0]
+        for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)p * P0 + q], ec[q], acc);
+      } else if (cx == 0) {
+        const double* g = G + off_G[c];   // G_{c,0}: [P_c][P0]; use its transpose
+        for (int q = 0; q < pc; ++q) acc = fma(g[(int64_t)q * P0 + p], ec[q], acc);
+      }
+    }
+    phis[p] = acc;
+  }
+  __syncthreads();
+  // J = 2 sum_P B[P] phi_P from the packed slices; F~ = F0 + h~ + J, both
+  // mirror elements written (as jbuild_packed_kernel)
+  const int n = fx.nbf, nt = n * (n + 1) / 2;
+  const double* bx = Bp + off_Bp[x];
+  for (int kk = threadIdx.x; kk < nt; kk += blockDim.x) {
+    const double* b = bx + kk;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int P = 0;
+#pragma unroll 4
+    for (; P + 4 <= fx.naux; P += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = fma(b[(int64_t)(P + u) * nt], phis[P + u], a4[u]);
+    for (; P < fx.naux; ++P) a4[0] = fma(b[(int64_t)P * nt], phis[P], a4[0]);
+    const double j2 = 2.0 * ((a4[0] + a4[1]) + (a4[2] + a4[3]));
+    int mu, nu;
+    tri_row_col(kk, n, mu, nu);
+    const int64_t o1 = fx.off_C + (int64_t)mu * n + nu, o2 = fx.off_C + (int64_t)nu * n + mu;
+    double v1 = j2, v2 = j2;
+    if (F0) { v1 += F0[o1]; v2 += F0[o2]; }
+    if (htilde) { v1 += htilde[o1]; v2 += htilde[o2]; }
+    out[o1] = v1;
+    if (mu != nu) out[o2] = v2;
+  }
+}
+
 hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double* Bp,
                                     hipStream_t st) {
   if (p.nfrag == 0) return hipSuccess;
@@ -377,16 +524,27 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
                      dim3(p.nfrag, (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW)), dim3(256), 0, st,
                      p.d_frag, p.d_off_Bp, p.d_off_tri, Bp, Dw, ws_d);
   const int etot = p.naux_cls_off.back();
+  const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
+  if (small_fragments(p)) {
+    // all fragments small: field and J fused (water: 320 threads)
+    const int jt = std::min(512, (ntmax + 63) / 64 * 64);
+    const size_t lds = ((size_t)(jt / 64) * etot + p.max_naux) * sizeof(double);
+    hipLaunchKernelGGL(field_jbuild_packed_kernel, dim3(p.nfrag), dim3(jt), lds, st, p.d_frag,
+                       p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
+                       p.d_naux_cls_off, ws_d, p.d_off_Bp, Bp, F0, htilde, out);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                      p.d_naux_cls_off, ws_d, ws_phi);
   // one block per fragment triangle when it fits 1024 threads (water: 320)
-  const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   const int jt = std::min(1024, (ntmax + 63) / 64 * 64);
   hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + jt - 1) / jt), dim3(jt), 0, st,
                      p.d_frag, p.d_off_Bp, Bp, ws_phi, F0, htilde, out);
   return hipGetLastError();
 }
+
+bool small_fragments(const fef_plan_s& p) { return p.max_nbf <= 32 && p.max_naux <= 80; }
 
 hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* Dw,
                           double* dD_max, hipStream_t st) {

@@ -1,0 +1,44 @@
+"""Host-side checks of bench.py's bookkeeping (no GPU): the flop counts its
+roofline uses, the multi-GPU refusal, and the traffic record lookup."""
+import json
+import os
+import subprocess
+import sys
+
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+import fefgen  # noqa: E402
+
+
+def test_pair_flop_counts_config0():
+    s = fefgen.make_system(0)
+    # 28 water pairs, 2 ov_x ov_y P0 each
+    assert bench.pair_flops(s) == 28 * 2 * 95 * 95 * 72
+    # issued: whole 96-row tiles; FP64 K = 72, split K = 3 * 72 rounded to 224
+    assert bench.pair_issued_flops(s, "f64") == 28 * 2 * 96 * 96 * 72
+    assert bench.pair_issued_flops(s, "fp16x2") == 28 * 2 * 96 * 96 * 224
+    assert bench.pair_issued_flops(s, "bf16x2") / bench.pair_flops(s) > 3.0
+
+
+def test_multi_gpu_request_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_record_matches_sources():
+    path = os.path.join(ROOT, "profiles", "pair_fp16x2_water4000-mixed_traffic.json")
+    rec = json.load(open(path))
+    got = bench.traffic_from_profiles("fp16x2", "water4000-mixed")
+    if rec["sources_hash"] == bench.kernel_sources_hash():
+        assert got == rec["bytes_per_launch"]
+        # fetched bytes are calibrated against a plain copy of known size
+        assert rec["fetch_scale"] > 0 and rec["write_scale"] > 0
+    else:
+        assert got is None
+    assert bench.traffic_from_profiles("fp16x2", "no-such-workload") is None
