@@ -126,3 +126,49 @@ def test_nucleobase_scf_step_and_half_transform_full_size():
     refw = s.G_of(1).T @ ref
     gotw = w.cpu().numpy()[:s.naux_class[0] * ov].reshape(-1, ov)
     np.testing.assert_allclose(gotw, refw, rtol=0, atol=1e-12)
+
+
+def test_surrogate_workload_full_size():
+    """8000 waters at 15 A (1,884,628 pairs), the surrogate workload: 10 SCF
+    steps, then surrogate passes with an ensemble whose statistics are fitted
+    on a sample of this box.  Threshold 0: every pair goes to the exact BF16x2
+    kernel through the masked path and the energies equal the plain exact pass
+    bitwise.  Threshold 1 Eh: pairs beyond 6 A are predicted (finite), pairs
+    within 6 A stay bitwise exact.  Sampled exact pairs against the oracle."""
+    import paper_1708_03377_amd as lib
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = fefgen.make_system(4)
+    _say("surrogate workload", s.nfrag, s.npair)
+    ctx = lib.Context(s)
+    ctx.scf(s.spec.niter)
+    p = PREC["bf16x2"]
+    exact = ctx.energies(p)[0].cpu().numpy().copy()
+    assert int(ctx.flags.cpu()[0]) == 0
+    rng = np.random.default_rng(4)
+    sample = np.sort(rng.choice(s.npair, 120, replace=False))
+    C = ctx.C.cpu().numpy(); eps = ctx.eps.cpu().numpy()
+    ref, _ = ofef.pair_energies(s, C, eps, pairs=(s.pair_x[sample], s.pair_y[sample],
+                                                  s.pair_s[sample]))
+    err = float(np.max(np.abs(exact[sample] - ref)))
+    _say(f"bf16x2 sampled max pair err {err:.3e}")
+    assert err <= 1e-6
+    U = ctx.invariants()
+    ens = lib.Ensemble(nmember=5, seed=1)
+    idx = torch.arange(0, s.npair, 97, dtype=torch.int32, device="cuda")
+    X, T = ctx.pair_features(U, idx, with_targets=True)
+    ens.fit_stats(X, T)
+    r6 = 6.0 * fefgen.BOHR_PER_ANGSTROM
+    near = (1.0 / s.pair_s) < r6
+    E2, tot, sel = ctx.surrogate_energies(ens, U, r6, 0.0, p)
+    E2 = E2.cpu().numpy(); sel = sel.cpu().numpy()
+    assert np.all(sel == 1)
+    assert np.array_equal(E2, exact)
+    E2, tot, sel = ctx.surrogate_energies(ens, U, r6, 1.0, p)
+    E2 = E2.cpu().numpy(); sel = sel.cpu().numpy()
+    assert np.all(sel[near] == 1)
+    assert np.array_equal(E2[near], exact[near])
+    assert np.all(np.isfinite(E2))
+    _say(f"predicted {float(np.mean(sel == 0)):.3f} of pairs at threshold 1 Eh, "
+         f"total {float(tot.cpu()[0]):.6f} vs exact {float(np.sum(exact)):.6f}")
