@@ -192,15 +192,29 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const int xs = 2 * pw + 8;
     uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
     uint16_t* R = right ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
-    // rows [ia][hi plane | lo plane]: consecutive threads take consecutive q
-    // so that the 2-byte stores of a wave are contiguous
+    // rows [ia][hi plane | lo plane | 8 zeros], written in 16-byte pieces: a
+    // thread splits eight consecutive q of one row and stores their hi and
+    // lo words; rows >= ov and q >= P0 are zeros, so no separate zero fill
+    const int nqc = pw / 8;
+    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     if (R)
-      for (int e = threadIdx.x; e < P0 * ov; e += 256) {
-        const int ia = e / P0, q = e - (e / P0) * P0;
-        uint16_t hi, lo;
-        split2<kF16>(Bs[q * kBld + ia] * sR, hi, lo);
-        R[ia * xs + q] = hi;
-        R[ia * xs + pw + q] = lo;
+      for (int e = threadIdx.x; e < kTile * (nqc + 1); e += 256) {
+        const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
+        if (c == nqc) {
+          *reinterpret_cast<u16x8*>(R + ia * xs + 2 * pw) = z8;
+          continue;
+        }
+        u16x8 h, l;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int q = 8 * c + u;
+          uint16_t hv = 0, lv = 0;
+          if (ia < ov && q < P0) split2<kF16>(Bs[q * kBld + ia] * sR, hv, lv);
+          h[u] = hv;
+          l[u] = lv;
+        }
+        *reinterpret_cast<u16x8*>(R + ia * xs + 8 * c) = h;
+        *reinterpret_cast<u16x8*>(R + ia * xs + pw + 8 * c) = l;
       }
     __syncthreads();  // Bs is rewritten with W^T below
     const int wld = P0 + 1;
@@ -217,21 +231,23 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < P0 * ov; e += 256) {
-      const int ia = e / P0, q = e - (e / P0) * P0;
-      uint16_t hi, lo;
-      split2<kF16>(Bs[ia * wld + q] * sL, hi, lo);
-      L[ia * xs + q] = hi;
-      L[ia * xs + pw + q] = lo;
-    }
-    // zeros: rows past ov, and the columns past P0 in each plane plus the tail
-    for (int e = threadIdx.x; e < kTile * xs; e += 256) {
-      const int m = e / xs, k = e - (e / xs) * xs;
-      const bool z = m >= ov || (k >= P0 && k < pw) || k >= pw + P0;
-      if (z) {
-        L[e] = 0;
-        if (R) R[e] = 0;
+    for (int e = threadIdx.x; e < kTile * (nqc + 1); e += 256) {
+      const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
+      if (c == nqc) {
+        *reinterpret_cast<u16x8*>(L + ia * xs + 2 * pw) = z8;
+        continue;
       }
+      u16x8 h, l;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = 8 * c + u;
+        uint16_t hv = 0, lv = 0;
+        if (ia < ov && q < P0) split2<kF16>(Bs[ia * wld + q] * sL, hv, lv);
+        h[u] = hv;
+        l[u] = lv;
+      }
+      *reinterpret_cast<u16x8*>(L + ia * xs + 8 * c) = h;
+      *reinterpret_cast<u16x8*>(L + ia * xs + pw + 8 * c) = l;
     }
   }
 }
