@@ -40,11 +40,17 @@ __device__ inline double weighted_tiles(const AccT (&acc)[TI][TJ], const double*
   return sum;
 }
 
-// Split-precision epilogue: FP32 weights 1/(Delta_x + Delta_y) from the
-// hardware reciprocal refined by one Newton step, r <- r (2 - d r) (error
-// about half an ulp, symmetric), FP32 squares summed over the 4 elements of
-// a tile, tile sums accumulated in FP64.  The column gaps gy may be stored in
-// FP32 or FP64 (converted on load).
+// Split-precision epilogue.  The four elements r = 0..3 that a lane holds
+// of one 16x16 tile share a column, and their weighted squares are summed as
+// one fraction over the product of the four FP32 denominators:
+//     sum_r v_r^2 / d_r = N / P,   P = (d0 d1)(d2 d3),
+//     N = d2 d3 (v0^2 d1 + v1^2 d0) + d0 d1 (v2^2 d3 + v3^2 d2),
+// so a tile costs one hardware reciprocal instead of four.  The quotient
+// q = N r is corrected once, q + r (N - P q) (error about half an ulp,
+// symmetric), and tile quotients are accumulated in FP64.  Magnitudes stay
+// inside FP32: the FP16 operand scales bound |v| by 2^28 K, and |d| is an
+// orbital-energy gap.  The column gaps gy may be stored in FP32 or FP64
+// (converted on load).
 template <int TI, int TJ, typename GyT>
 __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float* gx,
                                             const GyT* gy, int lane) {
@@ -61,16 +67,18 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
   for (int i = 0; i < TI; ++i)
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      float t = 0.0f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float d = dx[i][r] + dy[j];
-        float w = __builtin_amdgcn_rcpf(d);
-        w = fmaf(w, fmaf(-d, w, 1.0f), w);
-        const float v = acc[i][j][r];
-        t = fmaf(v * v, w, t);
-      }
-      sum += (double)t;
+      const float d0 = dx[i][0] + dy[j], d1 = dx[i][1] + dy[j];
+      const float d2 = dx[i][2] + dy[j], d3 = dx[i][3] + dy[j];
+      const float v0 = acc[i][j][0], v1 = acc[i][j][1];
+      const float v2 = acc[i][j][2], v3 = acc[i][j][3];
+      const float n01 = fmaf(v0 * v0, d1, (v1 * v1) * d0);
+      const float n23 = fmaf(v2 * v2, d3, (v3 * v3) * d2);
+      const float a = d0 * d1, b = d2 * d3;
+      const float num = fmaf(b, n01, a * n23);
+      const float den = a * b;
+      const float r = __builtin_amdgcn_rcpf(den);
+      const float q = num * r;
+      sum += (double)fmaf(r, fmaf(-den, q, num), q);
     }
   return sum;
 }
