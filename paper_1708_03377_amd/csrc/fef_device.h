@@ -23,6 +23,33 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// DPP move of a double within rows of 16 lanes (both halves moved with the
+// same control); every lane has a source for the controls used here.
+template <int kCtrl>
+__device__ inline double dpp_row_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double readlane_f64(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave sum without LDS traffic: DPP butterflies inside each row of 16 lanes
+// (quad swaps, then rotations by 4 and 8), then the four row sums read as
+// scalars and added in a fixed order.  The result is uniform across the wave.
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_row_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_row_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_row_f64<0x124>(v);  // row_ror 4
+  v += dpp_row_f64<0x128>(v);  // row_ror 8
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));

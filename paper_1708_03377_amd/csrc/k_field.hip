@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const FragInfo* __restrict
   }
 #pragma unroll
   for (int k = 0; k < kMomQ; ++k) {
-    const double t = wave_sum(acc[k]);
+    const double t = wave_sum_dpp(acc[k]);
     if (lane == 0 && k < nq) dmom[fi.off_aux + q0 + k] = t;
   }
 }
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
   }
 #pragma unroll
   for (int q = 0; q < kMomQW; ++q) {
-    const double t = wave_sum(acc[q]);
+    const double t = wave_sum_dpp(acc[q]);
     if (lane == 0 && q < nq) dmom[fi.off_aux + q0 + q] = t;
   }
 }

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256 * XB) void pair_plain_kernel(
 #pragma unroll
             for (int j = 0; j < 3; ++j) acc[i][j] = Mfma<T>::mma(xa[i][st], b[j], acc[i][j]);
         }
-        mine = wave_sum(weighted_tiles<sizeof(T) == 8, 3, 3>(acc, Gx + unit * kTile + r0,
+        mine = wave_sum_dpp(weighted_tiles<sizeof(T) == 8, 3, 3>(acc, Gx + unit * kTile + r0,
                                                               Gc + c0, lane, 1.0));
       }
       if (lane == 0) red[cur][wave] = mine;

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
           part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0, Gc + 16 * jh * TJP,
                                              lane);
         }
-        mine = wave_sum(part);
+        mine = wave_sum_dpp(part);
       }
       if (lane == 0) red[cur][wave] = mine;
       // the copy into the next buffer has landed (this wave's part), and
