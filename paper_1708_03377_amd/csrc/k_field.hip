@@ -295,22 +295,29 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
 #pragma unroll
   for (int q = 0; q < kMomQW; ++q) acc[q] = 0.0;
   if ((nt & 1) == 0 && (ob & 1) == 0 && (od & 1) == 0 && nt <= 384) {
+    // every load unconditional, so that all 24 are in flight together: rows
+    // past nq re-read row nq - 1 (their sums are not stored), and positions
+    // past nt re-read the row's last pair with density weight 0 (adding
+    // +-0 leaves the sum unchanged)
     double2 dv[3];
+    int kc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int k = 2 * lane + 128 * c;
+      kc[c] = min(k, nt - 2);
       dv[c] = k < nt ? *reinterpret_cast<const double2*>(d + k) : double2{0.0, 0.0};
     }
+    double2 bv[kMomQW][3];
 #pragma unroll
     for (int q = 0; q < kMomQW; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int k = 2 * lane + 128 * c;
-        if (q < nq && k < nt) {
-          const double2 bv = *reinterpret_cast<const double2*>(b + (int64_t)q * nt + k);
-          acc[q] = fma(bv.y, dv[c].y, fma(bv.x, dv[c].x, acc[q]));
-        }
-      }
+      for (int c = 0; c < 3; ++c)
+        bv[q][c] = *reinterpret_cast<const double2*>(b + (int64_t)min(q, nq - 1) * nt + kc[c]);
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
+#pragma unroll
+    for (int q = 0; q < kMomQW; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[q] = fma(bv[q][c].y, dv[c].y, fma(bv[q][c].x, dv[c].x, acc[q]));
   } else {
     for (int k = lane; k < nt; k += 64) {
       const double dk = d[k];
