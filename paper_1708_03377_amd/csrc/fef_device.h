@@ -17,6 +17,9 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
 
+// LDS (address space 3) destination of global_load_lds copies
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

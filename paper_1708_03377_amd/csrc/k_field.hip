@@ -262,11 +262,21 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
   const double* b = B + fi.off_B;
   const int64_t base = off_Bp[ch.frag];
   const int e0 = (int)(ch.begin - base), e1 = (int)(ch.end - base);
-  for (int e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int P = e / nt, k = e - (e / nt) * nt;
-    int mu, nu;
-    tri_row_col(k, n, mu, nu);
-    Bp[base + e] = b[P * n * n + mu * n + nu];
+  // eight loads per thread in flight: addresses of elements past the chunk
+  // are clamped to its last element and their values are not stored
+  for (int eb = e0 + threadIdx.x; eb < e1; eb += 256 * 8) {
+    double v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(eb + 256 * u, e1 - 1);
+      const int P = e / nt, k = e - (e / nt) * nt;
+      int mu, nu;
+      tri_row_col(k, n, mu, nu);
+      v8[u] = b[P * n * n + mu * n + nu];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (eb + 256 * u < e1) Bp[base + eb + 256 * u] = v8[u];
   }
 }
 

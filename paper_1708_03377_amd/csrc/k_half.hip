@@ -33,24 +33,39 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
                                                           const double* __restrict__ C,
                                                           double* __restrict__ bov, int max_nn) {
   extern __shared__ double sm[];
+  const int cs_ld = (max_nn + 1) & ~1;              // keeps Bst 16-byte aligned
   double* Cs = sm;                                  // [nbf][nbf]
-  double* Bst = sm + max_nn;                        // [8][nbf][nbf]
-  double* Xs = sm + (1 + kSliceGroup) * max_nn;     // [8][nocc][nbf]
+  double* Bst = sm + cs_ld;                         // [8][nbf][nbf]
+  double* Xs = sm + cs_ld + kSliceGroup * max_nn;   // [8][nocc][nbf]
   const FragInfo fi = frag[list[blockIdx.x]];
   const int p0 = blockIdx.y * kSliceGroup;
   if (p0 >= fi.naux) return;
   const int np = min(kSliceGroup, fi.naux - p0);
   const int n = fi.nbf, o = fi.nocc, v = fi.nvir, ov = fi.ov, nn = n * n;
-  for (int e = threadIdx.x; e < nn; e += 256) Cs[e] = C[fi.off_C + e];
   const double* src = B + fi.off_B + (int64_t)p0 * nn;
-  const int tot = np * nn;  // nn is even unless n is odd; stage in pairs when aligned
-  if ((nn & 1) == 0 && ((fi.off_B + (int64_t)p0 * nn) & 1) == 0) {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
-    double2* d2 = reinterpret_cast<double2*>(Bst);
-    for (int e = threadIdx.x; e < tot / 2; e += 256) d2[e] = s2[e];
+  const int tot = np * nn;
+  if ((tot & 1) == 0 && ((fi.off_B + (int64_t)p0 * nn) & 1) == 0) {
+    // the slices go straight into LDS, 16 bytes per lane, every piece of
+    // the block in flight at once (wave w moves the 1 KB pieces w, w + 4, ...)
+    const int nch = tot / 2, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int g = wave; g * 64 < nch; g += 4) {
+      const int c = g * 64 + lane;
+      if (c < nch)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 2 * (int64_t)c),
+                                         (lds_void_t*)(Bst + 128 * g), 16, 0, 0);
+    }
   } else {
     for (int e = threadIdx.x; e < tot; e += 256) Bst[e] = src[e];
   }
+  {  // C (nn <= 1024): four loads per thread in flight, clamped addresses
+    double cv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cv[u] = C[fi.off_C + min((int)threadIdx.x + 256 * u, nn - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if ((int)threadIdx.x + 256 * u < nn) Cs[threadIdx.x + 256 * u] = cv[u];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int e = threadIdx.x; e < np * o * n; e += 256) {  // X = C_occ^T B_P
     const int pp = e / (o * n), r = e - pp * (o * n);
@@ -342,7 +357,8 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
   if (!p.ht_fused.empty()) {
     double* wo = dense_out ? w : nullptr;
     const dim3 grid((unsigned)p.ht_fused.size());
-    const size_t lds = (size_t)((1 + kSliceGroup) * p.fuse_lds[0] + kSliceGroup * p.fuse_lds[1]) *
+    const size_t lds = (size_t)(((p.fuse_lds[0] + 1) & ~1) + kSliceGroup * p.fuse_lds[0] +
+                                kSliceGroup * p.fuse_lds[1]) *
                        sizeof(double);
     hipLaunchKernelGGL(ht_mo_small_kernel,
                        dim3(grid.x, (p.max_naux_small + kSliceGroup - 1) / kSliceGroup),

@@ -149,7 +149,6 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
 // MFMA operand lane layout (16x16x32): row (or column) = lane % 16,
 // contraction indices 8 (lane / 16) .. +7.
 constexpr int kXsMax = 2 * 80 + 8;  // row stride bound (pw <= 80)
-typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <bool kFp16, int XB, int NCH>
 __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
