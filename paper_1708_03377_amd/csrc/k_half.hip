@@ -102,9 +102,23 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
   const FragInfo fi = frag[f];
   const int ov = fi.ov, P = fi.naux;
   const int P4 = (P + 3) & ~3;
-  for (int e = threadIdx.x; e < P4 * kTile; e += 256) {
-    const int pp = e / kTile, ia = e - (e / kTile) * kTile;
-    Bs[pp * kBld + ia] = (pp < P && ia < ov) ? bov[fi.off_bov + (int64_t)pp * ov + ia] : 0.0;
+  // sixteen loads per thread in flight: positions outside B_ov load its first
+  // element and store zero
+  for (int eb = threadIdx.x; eb < P4 * kTile; eb += 256 * 16) {
+    double v16[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = eb + 256 * u;
+      const int pp = e / kTile, ia = e - (e / kTile) * kTile;
+      const bool in = e < P4 * kTile && pp < P && ia < ov;
+      const double x = bov[fi.off_bov + (in ? (int64_t)pp * ov + ia : 0)];
+      v16[u] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = eb + 256 * u;
+      if (e < P4 * kTile) Bs[(e / kTile) * kBld + (e - (e / kTile) * kTile)] = v16[u];
+    }
   }
   __syncthreads();
   // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia
