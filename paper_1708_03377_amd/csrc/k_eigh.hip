@@ -369,17 +369,37 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
   const int64_t oc = active ? frag[f].off_C : 0;
   double* s1 = S1[h];
   double* s2 = S2[h];
-  // ---- warm start: S1 = C, S2 = F_sym C, then A = C^T (F C)
-  for (int e = t; e < M * M; e += 32) {
-    const int i = e / M, j = e - (e / M) * M;
-    s1[i * LD + j] = (i < n && j < n) ? C[oc + i * n + j] : 0.0;
+  // ---- warm start: S1 = C, S2 = F_sym C, then A = C^T (F C).  Global
+  // loads are unconditional (positions outside the matrix read its first
+  // element and are replaced by zero), so that each lane's loads are in
+  // flight together.
+  {
+    constexpr int kPer = (M * M + 31) / 32;
+    double cv[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = t + 32 * u, i = e / M, j = e - (e / M) * M;
+      const bool in = e < M * M && i < n && j < n;
+      const double x = C[oc + (in ? i * n + j : 0)];
+      cv[u] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = t + 32 * u, i = e / M, j = e - (e / M) * M;
+      if (e < M * M) s1[i * LD + j] = cv[u];
+    }
   }
   __syncthreads();
   if (t < M) {
-    double frow[M];
+    double frow[M], fcol[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k)
-      frow[k] = (t < n && k < n) ? 0.5 * (F[oc + t * n + k] + F[oc + k * n + t]) : 0.0;
+    for (int k = 0; k < M; ++k) {
+      const bool in = t < n && k < n;
+      frow[k] = F[oc + (in ? t * n + k : 0)];
+      fcol[k] = F[oc + (in ? k * n + t : 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) frow[k] = (t < n && k < n) ? 0.5 * (frow[k] + fcol[k]) : 0.0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       double acc = 0.0;
@@ -502,14 +522,20 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
   __syncthreads();
   double dmax = 0.0;
   if (t < n) {
-    for (int j = 0; j < n; ++j) {
-      double acc = 0.0;
-      for (int k = 0; k < nocc; ++k) {
-        const int sl = occ[h][k];
-        acc = fma(s1[t * LD + sl], s1[j * LD + sl], acc);
+    double dold[M];  // this lane's row of the previous density, loaded up front
+#pragma unroll
+    for (int j = 0; j < M; ++j) dold[j] = Dold[oc + t * n + (j < n ? j : 0)];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j < n) {
+        double acc = 0.0;
+        for (int k = 0; k < nocc; ++k) {
+          const int sl = occ[h][k];
+          acc = fma(s1[t * LD + sl], s1[j * LD + sl], acc);
+        }
+        Dnew[oc + t * n + j] = acc;
+        dmax = fmax(dmax, fabs(acc - dold[j]));
       }
-      Dnew[oc + t * n + j] = acc;
-      dmax = fmax(dmax, fabs(acc - Dold[oc + t * n + j]));
     }
   }
 #pragma unroll
