@@ -146,19 +146,24 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
   d4 acc[kTilesPerWave];
 #pragma unroll
   for (int k = 0; k < kTilesPerWave; ++k) acc[k] = d4{0, 0, 0, 0};
+  // every tile of the wave is contracted, also tiles past NT (their B
+  // columns are in range and their A values finite; they are never
+  // stored), so that a k step's eight LDS reads are issued before its MFMAs
 #pragma unroll
   for (int ks = 0; ks < kSteps; ++ks) {
-    if (4 * ks >= P4) break;
+    if (4 * ks >= P4) break;  // rows past P4 are not staged
     const int pp = 4 * ks + lk;
+    double bv[kTilesPerWave];
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
-      const int tt = t0 + k;
-      if (tt < NT) {
-        const int qt = tt / kIT, it = tt - qt * kIT;
-        const double av = qt == qa ? ga[0][ks] : ga[1][ks];
-        const double bv = Bs[pp * kBld + 16 * it + li];
-        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[k], 0, 0, 0);
-      }
+      const int tt = t0 + k, qt = tt / kIT, it = tt - qt * kIT;
+      bv[k] = Bs[pp * kBld + 16 * it + li];
+    }
+#pragma unroll
+    for (int k = 0; k < kTilesPerWave; ++k) {
+      const int qt = (t0 + k) / kIT;
+      const double av = qt == qa ? ga[0][ks] : ga[1][ks];
+      acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[k], acc[k], 0, 0, 0);
     }
   }
   // element (r) of tile k: q = 16 qt + lk + 4 r, ia = 16 it + li
