@@ -17,15 +17,17 @@ namespace fef {
 
 // Half transform of small fragments (nbf <= 32, one 96-wide tile, P_c <= 80)
 // in two kernels.
-//  ht_mo_small_kernel: one workgroup per (fragment, 8 factor slices): the 8
-//    slices of B^x (8 nbf^2 doubles) are staged in LDS with 16-byte loads,
-//    then X = C_occ^T B_P and B_ov = X C_vir are formed from LDS and B_ov is
-//    written densely.  Thousands of workgroups keep HBM streaming.
+//  ht_mo_small_kernel: one workgroup per (fragment, kSliceGroup factor
+//    slices): the slices of B^x are copied into LDS (global_load_lds, 16
+//    bytes per lane), then X = C_occ^T B_P and B_ov = X C_vir are formed
+//    from LDS and B_ov is written densely.  Small groups keep the LDS of a
+//    workgroup at 27 KB (nbf = 24), so five share a CU and the copies of
+//    some overlap the contractions of others.
 //  ht_pack_small_kernel: one workgroup per fragment: B_ov^x in LDS, W^x =
 //    G^T B_ov^x on FP64 MFMA (accumulators stay in registers), and both
 //    pair-kernel operands of mode PREC written directly (FP16 scales from
 //    block-wide maxima).
-constexpr int kSmallP = 80, kSliceGroup = 8;
+constexpr int kSmallP = 80, kSliceGroup = 4;
 
 __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __restrict__ frag,
                                                           const int32_t* __restrict__ list,
@@ -35,8 +37,8 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
   extern __shared__ double sm[];
   const int cs_ld = (max_nn + 1) & ~1;              // keeps Bst 16-byte aligned
   double* Cs = sm;                                  // [nbf][nbf]
-  double* Bst = sm + cs_ld;                         // [8][nbf][nbf]
-  double* Xs = sm + cs_ld + kSliceGroup * max_nn;   // [8][nocc][nbf]
+  double* Bst = sm + cs_ld;                         // [kSliceGroup][nbf][nbf]
+  double* Xs = sm + cs_ld + kSliceGroup * max_nn;   // [kSliceGroup][nocc][nbf]
   const FragInfo fi = frag[list[blockIdx.x]];
   const int p0 = blockIdx.y * kSliceGroup;
   if (p0 >= fi.naux) return;
@@ -72,6 +74,7 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
     const int i = r / n, nu = r - (r / n) * n;
     const double* b = Bst + pp * nn + nu;
     double acc = 0.0;
+#pragma unroll 8
     for (int mu = 0; mu < n; ++mu) acc = fma(Cs[mu * n + i], b[mu * n], acc);
     Xs[e] = acc;
   }
@@ -81,6 +84,7 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
     const int i = r / v, a = r - (r / v) * v;
     const double* xr = Xs + (pp * o + i) * n;
     double acc = 0.0;
+#pragma unroll 8
     for (int nu = 0; nu < n; ++nu) acc = fma(xr[nu], Cs[nu * n + o + a], acc);
     bov[fi.off_bov + (int64_t)(p0 + pp) * ov + r] = acc;
   }
