@@ -41,6 +41,14 @@ def ragged_system(seed=21):
     return fefgen.make_random_system(seed, sizes, naux=6)
 
 
+def odd_system(seed=23):
+    # odd nbf with an odd number of factor slices (P = 5): slice groups of
+    # the half transform start at odd offsets of the coefficient pool, so
+    # both its 16-byte copy and its element-wise fallback run
+    sizes = [(7, 3), (5, 2), (9, 4), (3, 1), (24, 5)]
+    return fefgen.make_random_system(seed, sizes, naux=5)
+
+
 def two_class_system(seed=22):
     # a 300-wide (4-tile) solute of class 1 with P1 = 20 among P0 = 8 solvent fragments
     return fefgen.make_two_class_system(seed, (40, 10, 20),
@@ -49,7 +57,7 @@ def two_class_system(seed=22):
 
 # ---------------------------------------------------------------------------
 def test_half_transform_matches_oracle(torch):
-    for sysm in (ragged_system(), two_class_system()):
+    for sysm in (ragged_system(), two_class_system(), odd_system()):
         _say("half transform", sysm.nfrag)
         ctx = ctx_for(sysm)
         bov = torch.zeros(max(ctx.sizes["bov"], 1), dtype=torch.float64, device="cuda")
@@ -71,10 +79,10 @@ def test_half_transform_matches_oracle(torch):
             ob += P * ov; ow += P0 * ov
 
 
-@pytest.mark.parametrize("which", ["ragged", "two_class", "config0"])
+@pytest.mark.parametrize("which", ["ragged", "two_class", "config0", "odd"])
 def test_pair_energies_f64(torch, which):
     sysm = {"ragged": ragged_system, "two_class": two_class_system,
-            "config0": lambda: fefgen.make_system(0)}[which]()
+            "config0": lambda: fefgen.make_system(0), "odd": odd_system}[which]()
     _say("pair energies f64", which, sysm.npair)
     ref, ref_tot = ofef.pair_energies(sysm)
     ctx = ctx_for(sysm)
