@@ -47,7 +47,8 @@ __device__ inline double weighted_tiles(const AccT (&acc)[TI][TJ], const double*
 //     N = d2 d3 (v0^2 d1 + v1^2 d0) + d0 d1 (v2^2 d3 + v3^2 d2),
 // so a tile costs one hardware reciprocal instead of four.  The quotient
 // q = N r is corrected once, q + r (N - P q) (error about half an ulp,
-// symmetric), and tile quotients are accumulated in FP64.  Magnitudes stay
+// symmetric); the TI x TJ tile quotients of a call (terms of one sign) are
+// summed in FP32 and the call's sum is returned for FP64 accumulation.  Magnitudes stay
 // inside FP32: the FP16 operand scales bound |v| by 2^28 K, and |d| is an
 // orbital-energy gap.  The column gaps gy may be stored in FP32 or FP64
 // (converted on load).
@@ -62,7 +63,7 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
     for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + 4 * lk + r];
 #pragma unroll
   for (int j = 0; j < TJ; ++j) dy[j] = (float)gy[16 * j + li];
-  double sum = 0.0;
+  float sum = 0.0f;
 #pragma unroll
   for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -78,9 +79,9 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
       const float den = a * b;
       const float r = __builtin_amdgcn_rcpf(den);
       const float q = num * r;
-      sum += (double)fmaf(r, fmaf(-den, q, num), q);
+      sum += fmaf(r, fmaf(-den, q, num), q);
     }
-  return sum;
+  return (double)sum;
 }
 
 }  // namespace fef
