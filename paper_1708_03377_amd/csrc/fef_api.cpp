@@ -449,7 +449,8 @@ fef_status fef_coulomb_field(fef_plan p, const double* B, const double* G, const
 static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, const double* G,
                                 const double* F0, const double* htilde, double* C, double* eps,
                                 double* D, double* dD_max, int32_t* flags, void* ws,
-                                size_t ws_bytes, void* stream) {
+                                size_t ws_bytes, void* stream, const double* B_pack = nullptr,
+                                double* Bp_out = nullptr) {
   if (!p) return FEF_E_ARG;
   if (!dD_max || !flags) return FEF_E_ARG;
   if (p->nfrag > 0 && (!(B || Bp) || !G || !F0 || !C || !eps)) return FEF_E_ARG;
@@ -466,7 +467,7 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   double* Dw = eigws + 2 * (int64_t)p->eig_large.size() * slot;
   hipError_t e = launch_density(*p, C, Dold, Bp ? Dw : nullptr, dD_max, st);
   if (e == hipSuccess && p->nfrag > 0)
-    e = Bp ? launch_field_packed(*p, Bp, G, Dw, F0, htilde, F, wd, wphi, st)
+    e = Bp ? launch_field_packed(*p, Bp, G, Dw, F0, htilde, F, wd, wphi, st, B_pack, Bp_out)
            : launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, F, Dold, C, eps, Dnew, dD_max, flags, eigws, st);
@@ -497,3 +498,16 @@ fef_status fef_scf_step_packed(fef_plan p, const double* Bp, const double* G, co
 }
 
 }  // extern "C"
+
+namespace fef {
+
+fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const double* G,
+                            const double* F0, const double* htilde, double* C, double* eps,
+                            double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                            void* stream) {
+  if (p && p->nfrag > 0 && (!B || !Bp)) return FEF_E_ARG;
+  return scf_step_impl(p, nullptr, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
+                       stream, B, Bp);
+}
+
+}  // namespace fef

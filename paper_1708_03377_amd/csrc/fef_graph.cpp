@@ -53,12 +53,15 @@ fef_status fef_graph_create(fef_plan p, const fef_pass_args* a, int32_t niter, f
       hipLaunchKernelGGL(copy_kernel, dim3(256), dim3(256), 0, st, a->C0, a->C, p->nC);
       hipLaunchKernelGGL(copy_kernel, dim3(64), dim3(256), 0, st, a->eps0, a->eps, p->nEps);
     }
-    if (a->Bp && niter > 0) status = fef_pack_coefficients(p, a->B, a->Bp, st);
+    // with a packed pool the first step packs B on the way (its moments
+    // kernel reads B and writes Bp), the later steps read Bp
     for (int it = 0; it < niter && status == FEF_OK; ++it)
-      status = a->Bp ? fef_scf_step_packed(p, a->Bp, a->G, a->F0, a->htilde, a->C, a->eps, a->D,
-                                           a->dD_max, a->flags, a->ws, a->ws_bytes, st)
-                     : fef_scf_step(p, a->B, a->G, a->F0, a->htilde, a->C, a->eps, a->D,
-                                    a->dD_max, a->flags, a->ws, a->ws_bytes, st);
+      status = !a->Bp ? fef_scf_step(p, a->B, a->G, a->F0, a->htilde, a->C, a->eps, a->D,
+                                     a->dD_max, a->flags, a->ws, a->ws_bytes, st)
+               : it == 0 ? scf_step_packing(p, a->B, a->Bp, a->G, a->F0, a->htilde, a->C, a->eps,
+                                            a->D, a->dD_max, a->flags, a->ws, a->ws_bytes, st)
+                         : fef_scf_step_packed(p, a->Bp, a->G, a->F0, a->htilde, a->C, a->eps,
+                                               a->D, a->dD_max, a->flags, a->ws, a->ws_bytes, st);
     if (status == FEF_OK)
       status = fef_half_transform(p, a->B, a->C, a->G, nullptr, nullptr, a->ops, prec, a->ws,
                                   a->ws_bytes, st);

@@ -190,11 +190,21 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
                                     hipStream_t st);
 // every fragment has nbf <= 32 and P <= 80 (the fused field + J kernel applies)
 bool small_fragments(const fef_plan_s& p);
+// B_pack non-null: the moments kernel reads the slices from B and writes
+// their packed copy to Bp_out (= Bp) on the way (the first step of a pass)
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
-                               double* out, double* ws_d, double* ws_phi, hipStream_t st);
+                               double* out, double* ws_d, double* ws_phi, hipStream_t st,
+                               const double* B_pack = nullptr, double* Bp_out = nullptr);
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st);
+// One packed SCF step that also writes the packed copy Bp of B (its moments
+// kernel reads the slices from B): the first step of a captured pass, in
+// place of packing followed by a packed step, with the same results.
+fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const double* G,
+                            const double* F0, const double* htilde, double* C, double* eps,
+                            double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                            void* stream);
 
 // Surrogate (k_mlp.hip).
 hipError_t launch_top_modes(const double* V, int n, double* Q, hipStream_t st);

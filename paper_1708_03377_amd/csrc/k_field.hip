@@ -282,58 +282,101 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
 
 // d^x_Q = sum_k Bp[Q][k] Dw[k] from the packed slices and the weighted
 // packed density.  Each wave takes kMomQW consecutive Q (four waves per
-// block); with 16-byte loads and triangles of at most 384 numbers (up to 27
-// basis functions) the k loop is unrolled, so that all of a wave's loads are
-// in flight together.
+// block); with triangles of at most 384 numbers (up to 27 basis functions)
+// the k loop is unrolled and every load is unconditional, so that all of a
+// wave's loads are in flight together.  kPack: the slice values are read
+// from B at their triangle positions and also written to Bp (the packing
+// of the first SCF step of a pass), in the same order as the packed
+// variant, so that Bp and d are bitwise those of packing then moments.
 constexpr int kMomQW = 8;
+template <bool kPack>
 __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
                                                              const int64_t* __restrict__ off_Bp,
                                                              const int64_t* __restrict__ off_tri,
-                                                             const double* __restrict__ Bp,
+                                                             const double* __restrict__ Bsrc,
                                                              const double* __restrict__ Dw,
-                                                             double* __restrict__ dmom) {
+                                                             double* __restrict__ dmom,
+                                                             const double* __restrict__ Bfull,
+                                                             double* __restrict__ Bp_out) {
   const FragInfo fi = frag[blockIdx.x];
   const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQW;
   if (q0 >= fi.naux) return;
   const int lane = threadIdx.x & 63;
   const int nq = min(kMomQW, fi.naux - q0);
-  const int n = fi.nbf, nt = n * (n + 1) / 2;
+  const int n = fi.nbf, nt = n * (n + 1) / 2, nn = n * n;
   const int64_t ob = off_Bp[blockIdx.x] + (int64_t)q0 * nt, od = off_tri[blockIdx.x];
-  const double* b = Bp + ob;
+  const double* b = kPack ? nullptr : Bsrc + ob;
+  const double* bf = kPack ? Bfull + fi.off_B + (int64_t)q0 * nn : nullptr;
+  double* bo = kPack ? Bp_out + ob : nullptr;
   const double* d = Dw + od;
   double acc[kMomQW];
 #pragma unroll
   for (int q = 0; q < kMomQW; ++q) acc[q] = 0.0;
   if ((nt & 1) == 0 && (ob & 1) == 0 && (od & 1) == 0 && nt <= 384) {
-    // every load unconditional, so that all 24 are in flight together: rows
-    // past nq re-read row nq - 1 (their sums are not stored), and positions
-    // past nt re-read the row's last pair with density weight 0 (adding
-    // +-0 leaves the sum unchanged)
+    // rows past nq re-read row nq - 1 (their sums are not stored), and
+    // positions past nt re-read the row's last pair with density weight 0
+    // (adding +-0 leaves the sum unchanged)
     double2 dv[3];
-    int kc[3];
+    int kc[3], s0[3], s1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int k = 2 * lane + 128 * c;
       kc[c] = min(k, nt - 2);
       dv[c] = k < nt ? *reinterpret_cast<const double2*>(d + k) : double2{0.0, 0.0};
+      if (kPack) {
+        int mu, nu;
+        tri_row_col(kc[c], n, mu, nu);
+        s0[c] = mu * n + nu;
+        tri_row_col(kc[c] + 1, n, mu, nu);
+        s1[c] = mu * n + nu;
+      }
     }
     double2 bv[kMomQW][3];
 #pragma unroll
     for (int q = 0; q < kMomQW; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        bv[q][c] = *reinterpret_cast<const double2*>(b + (int64_t)min(q, nq - 1) * nt + kc[c]);
+      for (int c = 0; c < 3; ++c) {
+        const int64_t row = min(q, nq - 1);
+        if (kPack) {
+          bv[q][c].x = bf[row * nn + s0[c]];
+          bv[q][c].y = bf[row * nn + s1[c]];
+        } else {
+          bv[q][c] = *reinterpret_cast<const double2*>(b + row * nt + kc[c]);
+        }
+      }
     __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
 #pragma unroll
     for (int q = 0; q < kMomQW; ++q)
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[q] = fma(bv[q][c].y, dv[c].y, fma(bv[q][c].x, dv[c].x, acc[q]));
+    if (kPack)
+#pragma unroll
+      for (int q = 0; q < kMomQW; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (q < nq && 2 * lane + 128 * c < nt)
+            *reinterpret_cast<double2*>(bo + (int64_t)q * nt + 2 * lane + 128 * c) = bv[q][c];
   } else {
     for (int k = lane; k < nt; k += 64) {
       const double dk = d[k];
+      int s = 0;
+      if (kPack) {
+        int mu, nu;
+        tri_row_col(k, n, mu, nu);
+        s = mu * n + nu;
+      }
 #pragma unroll
       for (int q = 0; q < kMomQW; ++q)
-        if (q < nq) acc[q] = fma(b[(int64_t)q * nt + k], dk, acc[q]);
+        if (q < nq) {
+          double v;
+          if (kPack) {
+            v = bf[(int64_t)q * nn + s];
+            bo[(int64_t)q * nt + k] = v;
+          } else {
+            v = b[(int64_t)q * nt + k];
+          }
+          acc[q] = fma(v, dk, acc[q]);
+        }
     }
   }
 #pragma unroll
@@ -536,10 +579,15 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
 
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
-                               double* out, double* ws_d, double* ws_phi, hipStream_t st) {
-  hipLaunchKernelGGL(moments_packed_kernel,
-                     dim3(p.nfrag, (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW)), dim3(256), 0, st,
-                     p.d_frag, p.d_off_Bp, p.d_off_tri, Bp, Dw, ws_d);
+                               double* out, double* ws_d, double* ws_phi, hipStream_t st,
+                               const double* B_pack, double* Bp_out) {
+  const dim3 mgrid(p.nfrag, (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW));
+  if (B_pack)
+    hipLaunchKernelGGL(moments_packed_kernel<true>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
+                       p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out);
+  else
+    hipLaunchKernelGGL(moments_packed_kernel<false>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
+                       p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr);
   const int etot = p.naux_cls_off.back();
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   if (small_fragments(p)) {

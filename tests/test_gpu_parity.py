@@ -218,7 +218,9 @@ def test_tilings_agree(torch, prec, tiles):
 
 def test_graph_replays_match_eager(torch):
     """A captured FEF pass replays bitwise like the eager calls, also with
-    eager work and synchronisations between replays."""
+    eager work and synchronisations between replays.  The packed coefficient
+    pool is poisoned before each replay: the pass packs B itself (in its
+    first SCF step) before anything reads the pool."""
     import paper_1708_03377_amd as lib
     for sysm, prec in ((fefgen.make_system(0), "f64"), (two_class_system(), "bf16x2")):
         ctx = ctx_for(sysm)
@@ -229,6 +231,7 @@ def test_graph_replays_match_eager(torch):
         g = ctx.graph(3, p)
         for rep in range(3):
             ctx.E2_pair.fill_(0.0); ctx.C.fill_(0.0)
+            ctx.packed_coefficients().fill_(float("nan"))
             ctx.launch(g)
             torch.cuda.synchronize()
             assert np.array_equal(ctx.E2_pair[:ctx.npair].cpu().numpy(), E_eager), rep
