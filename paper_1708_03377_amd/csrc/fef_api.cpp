@@ -446,31 +446,53 @@ fef_status fef_coulomb_field(fef_plan p, const double* B, const double* G, const
                                  static_cast<hipStream_t>(stream)));
 }
 
+// Workspace of an SCF step (doubles): field scratch, then Dold [nC], F [nC],
+// a spare density pool [nC] (Dnew when the caller passes no D), the
+// eigensolver slots, the weighted packed density Dw.
+struct ScfWs {
+  double *wd, *wphi, *Dold, *F, *Dspare, *eigws, *Dw;
+};
+static ScfWs scf_ws(const fef_plan_s& p, void* ws) {
+  ScfWs w;
+  w.wd = static_cast<double*>(ws);
+  w.wphi = w.wd + naux_total(p);
+  w.Dold = static_cast<double*>(ws) + field_ws_bytes(p) / (int64_t)sizeof(double);
+  w.F = w.Dold + std::max<int64_t>(p.nC, 1);
+  w.Dspare = w.F + std::max<int64_t>(p.nC, 1);
+  w.eigws = w.F + 2 * std::max<int64_t>(p.nC, 1);
+  const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
+  w.Dw = w.eigws + 2 * (int64_t)p.eig_large.size() * slot;
+  return w;
+}
+
+// One SCF step.  B_pack / Bp_out: the moments kernel packs B into Bp on the
+// way.  carry_out: the eigensolver also writes Dw of its orbitals.  Dprev
+// non-null: D and Dw of the current orbitals are already in Dprev and the
+// workspace (the previous step carried them), no density kernel.  Dout
+// non-null: the new density goes there (never the same pool as Dprev).
 static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, const double* G,
                                 const double* F0, const double* htilde, double* C, double* eps,
                                 double* D, double* dD_max, int32_t* flags, void* ws,
                                 size_t ws_bytes, void* stream, const double* B_pack = nullptr,
-                                double* Bp_out = nullptr) {
+                                double* Bp_out = nullptr, bool carry_out = false,
+                                const double* Dprev = nullptr, double* Dout = nullptr) {
   if (!p) return FEF_E_ARG;
   if (!dD_max || !flags) return FEF_E_ARG;
   if (p->nfrag > 0 && (!(B || Bp) || !G || !F0 || !C || !eps)) return FEF_E_ARG;
   if ((int64_t)ws_bytes < scf_ws_bytes(*p) || !ws) return FEF_E_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  double* wd = static_cast<double*>(ws);
-  double* wphi = wd + naux_total(*p);
-  double* base = static_cast<double*>(ws) + field_ws_bytes(*p) / (int64_t)sizeof(double);
-  double* Dold = base;
-  double* F = Dold + std::max<int64_t>(p->nC, 1);
-  double* Dnew = D ? D : F + std::max<int64_t>(p->nC, 1);
-  double* eigws = F + 2 * std::max<int64_t>(p->nC, 1);
-  const int64_t slot = (int64_t)(p->eig_large_max_nbf + 1) * (p->eig_large_max_nbf + 1);
-  double* Dw = eigws + 2 * (int64_t)p->eig_large.size() * slot;
-  hipError_t e = launch_density(*p, C, Dold, Bp ? Dw : nullptr, dD_max, st);
+  const ScfWs w = scf_ws(*p, ws);
+  const double* Dold = Dprev ? Dprev : w.Dold;
+  double* Dnew = Dout ? Dout : (D ? D : w.Dspare);
+  hipError_t e = Dprev ? launch_zero_scalar(dD_max, st)
+                       : launch_density(*p, C, w.Dold, Bp ? w.Dw : nullptr, dD_max, st);
   if (e == hipSuccess && p->nfrag > 0)
-    e = Bp ? launch_field_packed(*p, Bp, G, Dw, F0, htilde, F, wd, wphi, st, B_pack, Bp_out)
-           : launch_field(*p, B, G, Dold, F0, htilde, F, wd, wphi, st);
+    e = Bp ? launch_field_packed(*p, Bp, G, w.Dw, F0, htilde, w.F, w.wd, w.wphi, st, B_pack,
+                                 Bp_out)
+           : launch_field(*p, B, G, Dold, F0, htilde, w.F, w.wd, w.wphi, st);
   if (e == hipSuccess && p->nfrag > 0)
-    e = launch_eigh(*p, F, Dold, C, eps, Dnew, dD_max, flags, eigws, st);
+    e = launch_eigh(*p, w.F, Dold, C, eps, Dnew, dD_max, flags, w.eigws, st,
+                    carry_out ? w.Dw : nullptr);
   return hip_status(e);
 }
 
@@ -508,6 +530,25 @@ fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const doubl
   if (p && p->nfrag > 0 && (!B || !Bp)) return FEF_E_ARG;
   return scf_step_impl(p, nullptr, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
                        stream, B, Bp);
+}
+
+bool density_carry_ok(const fef_plan_s& p) { return p.max_nbf <= 32; }
+
+fef_status scf_step_carry(fef_plan p, const double* B_pack, double* Bp, const double* G,
+                          const double* F0, const double* htilde, double* C, double* eps,
+                          double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                          void* stream, int step, int nsteps) {
+  if (!p || !D || !ws || !density_carry_ok(*p) || step < 0 || step >= nsteps) return FEF_E_ARG;
+  if (p->nfrag > 0 && !Bp) return FEF_E_ARG;
+  if (step > 0 && B_pack) return FEF_E_ARG;  // the packing step starts a pass
+  if ((int64_t)ws_bytes < scf_ws_bytes(*p)) return FEF_E_WORKSPACE;
+  // the new densities alternate between the spare pool and D so that the
+  // last step's lands in D and no step reads the pool it writes
+  double* spare = scf_ws(*p, ws).Dspare;
+  auto target = [&](int s) { return ((nsteps - 1 - s) % 2 == 0) ? D : spare; };
+  return scf_step_impl(p, nullptr, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
+                       stream, B_pack, B_pack ? Bp : nullptr, true,
+                       step > 0 ? target(step - 1) : nullptr, target(step));
 }
 
 }  // namespace fef

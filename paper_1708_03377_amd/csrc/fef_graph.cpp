@@ -54,10 +54,15 @@ fef_status fef_graph_create(fef_plan p, const fef_pass_args* a, int32_t niter, f
       hipLaunchKernelGGL(copy_kernel, dim3(64), dim3(256), 0, st, a->eps0, a->eps, p->nEps);
     }
     // with a packed pool the first step packs B on the way (its moments
-    // kernel reads B and writes Bp), the later steps read Bp
+    // kernel reads B and writes Bp), the later steps read Bp; with small
+    // fragments and a D pool each step also carries its density to the next
+    const bool carry = a->Bp && a->D && density_carry_ok(*p);
     for (int it = 0; it < niter && status == FEF_OK; ++it)
       status = !a->Bp ? fef_scf_step(p, a->B, a->G, a->F0, a->htilde, a->C, a->eps, a->D,
                                      a->dD_max, a->flags, a->ws, a->ws_bytes, st)
+               : carry ? scf_step_carry(p, it == 0 ? a->B : nullptr, a->Bp, a->G, a->F0,
+                                        a->htilde, a->C, a->eps, a->D, a->dD_max, a->flags,
+                                        a->ws, a->ws_bytes, st, it, niter)
                : it == 0 ? scf_step_packing(p, a->B, a->Bp, a->G, a->F0, a->htilde, a->C, a->eps,
                                             a->D, a->dD_max, a->flags, a->ws, a->ws_bytes, st)
                          : fef_scf_step_packed(p, a->Bp, a->G, a->F0, a->htilde, a->C, a->eps,

@@ -180,9 +180,12 @@ hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, doubl
 hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
                         const double* D, const double* F0, const double* htilde,
                         double* out, double* ws_d, double* ws_phi, hipStream_t st);
+// Dw non-null (only when every fragment has nbf <= 32): the register-
+// resident solvers also write the weighted packed density of the new
+// orbitals, bitwise as launch_density forms it, for the next step
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* C, double* eps, double* Dnew, double* dD_max,
-                       int32_t* flags, double* ws_eig, hipStream_t st);
+                       int32_t* flags, double* ws_eig, hipStream_t st, double* Dw = nullptr);
 hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, const double* F,
                            const double* Dold, double* C, double* eps, double* Dnew,
                            double* dmax, int32_t* flags, double* ws_eig, hipStream_t st);
@@ -190,6 +193,7 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
                                     hipStream_t st);
 // every fragment has nbf <= 32 and P <= 80 (the fused field + J kernel applies)
 bool small_fragments(const fef_plan_s& p);
+hipError_t launch_zero_scalar(double* x, hipStream_t st);  // *x = 0 (a kernel, not a memset)
 // B_pack non-null: the moments kernel reads the slices from B and writes
 // their packed copy to Bp_out (= Bp) on the way (the first step of a pass)
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
@@ -205,6 +209,17 @@ fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const doubl
                             const double* F0, const double* htilde, double* C, double* eps,
                             double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
                             void* stream);
+// Packed SCF steps of a captured pass when every fragment has nbf <= 32
+// (step = 0 .. nsteps - 1; B_pack non-null only for step 0, which packs B
+// into Bp on the way): each step's eigensolver also leaves the weighted
+// packed density of its orbitals in the workspace, so the next step runs
+// no density kernel.  The densities alternate between a spare workspace
+// pool and D, the last step's landing in D.  Same results as packed steps.
+bool density_carry_ok(const fef_plan_s& p);
+fef_status scf_step_carry(fef_plan p, const double* B_pack, double* Bp, const double* G,
+                          const double* F0, const double* htilde, double* C, double* eps,
+                          double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
+                          void* stream, int step, int nsteps);
 
 // Surrogate (k_mlp.hip).
 hipError_t launch_top_modes(const double* V, int n, double* Q, hipStream_t st);

@@ -351,7 +351,7 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list, int32_t count,
     const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
     double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
-    int32_t* __restrict__ flags) {
+    int32_t* __restrict__ flags, const int64_t* __restrict__ off_tri, double* __restrict__ Dw) {
   static_assert(M % 2 == 0 && M >= 2 && M <= 32, "half-wave matrix size");
   constexpr int LD = M + 1;
   __shared__ double S1[2][M * LD];
@@ -534,6 +534,9 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
           acc = fma(s1[t * LD + sl], s1[j * LD + sl], acc);
         }
         Dnew[oc + t * n + j] = acc;
+        // the weighted packed copy, exactly as the density kernel forms it
+        if (Dw && t <= j)
+          Dw[off_tri[f] + t * n - t * (t - 1) / 2 + (j - t)] = (t == j ? 1.0 : 2.0) * acc;
         dmax = fmax(dmax, fabs(acc - dold[j]));
       }
     }
@@ -775,7 +778,7 @@ static size_t eig_scratch_bytes(int n) {
 
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold, double* C,
                        double* eps, double* Dnew, double* dD_max, int32_t* flags,
-                       double* ws_eig, hipStream_t st) {
+                       double* ws_eig, hipStream_t st, double* Dw) {
   // n <= 32: register-resident kernels, one size class per launch
   {
     const int sizes[4] = {8, 16, 24, 32};
@@ -786,7 +789,7 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
       const int32_t* lst = p.d_eig_small + b;
 #define FEF_EIGW(MM)                                                                          \
   hipLaunchKernelGGL((eigh_wave_kernel<MM>), grid, dim3(64), 0, st, p.d_frag, lst, cnt, F,    \
-                     Dold, C, eps, Dnew, dD_max, flags)
+                     Dold, C, eps, Dnew, dD_max, flags, p.d_off_tri, Dw)
       switch (sizes[c]) {
         case 8: FEF_EIGW(8); break;
         case 16: FEF_EIGW(16); break;

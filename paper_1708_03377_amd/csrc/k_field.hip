@@ -611,6 +611,11 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
 
 bool small_fragments(const fef_plan_s& p) { return p.max_nbf <= 32 && p.max_naux <= 80; }
 
+hipError_t launch_zero_scalar(double* x, hipStream_t st) {
+  hipLaunchKernelGGL(zero_scalar_kernel, dim3(1), dim3(1), 0, st, x);
+  return hipGetLastError();
+}
+
 hipError_t launch_density(const fef_plan_s& p, const double* C, double* D, double* Dw,
                           double* dD_max, hipStream_t st) {
   if (p.nfrag == 0) {
