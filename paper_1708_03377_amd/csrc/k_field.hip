@@ -514,13 +514,37 @@ __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
   __syncthreads();
   double* phis = part + NW * etot;
   const FragInfo fx = frag[x];
-  const int cx = fx.cls;
-  for (int p = threadIdx.x; p < fx.naux; p += blockDim.x) {
-    double acc = 0.0;
+  const int cx = fx.cls, naux = fx.naux;
+  const int pc0 = naux_cls_off[1] - naux_cls_off[0], qs = (pc0 + 3) / 4;
+  double* red4 = part + etot;
+  const bool quarter = cx == 0 && 4 * naux <= (int)blockDim.x && 4 * naux <= (NW - 1) * etot;
+  if (quarter) {
+    const int g = threadIdx.x / naux, p = threadIdx.x - g * naux;
+    if (g < 4) {
+      const double* e0c = part + naux_cls_off[0];
+      const int q1 = min(pc0, (g + 1) * qs);
+      double acc = 0.0;
+      int q = g * qs;
+      for (; q + 8 <= q1; q += 8) {
+        double g8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g8[u] = G[(int64_t)(q + u) * P0 + p];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(g8[u], e0c[q + u], acc);
+      }
+      for (; q < q1; ++q) acc = fma(G[(int64_t)q * P0 + p], e0c[q], acc);
+      red4[g * naux + p] = acc;
+    }
+    __syncthreads();
+  }
+  for (int p = threadIdx.x; p < naux; p += blockDim.x) {
+    double acc = quarter ? (red4[p] + red4[naux + p]) + (red4[2 * naux + p] + red4[3 * naux + p]) : 0.0;
     for (int c = 0; c < nclass; ++c) {
       const int pc = naux_cls_off[c + 1] - naux_cls_off[c];
       const double* ec = part + naux_cls_off[c];
-      if (c == 0 && cx == 0) {
+      if (c == 0 && cx == 0 && quarter) {
+        continue;
+      } else if (c == 0 && cx == 0) {
         // G_{0,0} is symmetric: read it by columns, so that consecutive
         // threads (rows p) load consecutive addresses; eight columns' loads
         // in flight at a time
@@ -548,6 +572,57 @@ __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
   // mirror elements written (as jbuild_packed_kernel)
   const int n = fx.nbf, nt = n * (n + 1) / 2;
   const double* bx = Bp + off_Bp[x];
+  const int H = nt / 2;
+  if ((nt & 1) == 0 && (off_Bp[x] & 1) == 0 && 2 * H <= (int)blockDim.x && nt <= NW * etot) {
+    // pairs of elements with 16-byte loads: threads [0, H) take the even
+    // slices, [H, 2H) the odd ones, and the two partial sums meet in LDS
+    // (the e_c area is free now)
+    double* jbuf = part;
+    const int tid = threadIdx.x, half = tid >= H ? 1 : 0, m = tid - half * H;
+    double2 acc2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc2[u] = double2{0.0, 0.0};
+    if (tid < 2 * H) {
+      const double* b = bx + 2 * m;
+      int P = half;
+      for (; P + 14 < fx.naux; P += 16) {
+        double2 bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) bv[u] = *reinterpret_cast<const double2*>(b + (int64_t)(P + 2 * u) * nt);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double ph = phis[P + 2 * u];
+          acc2[u & 3].x = fma(bv[u].x, ph, acc2[u & 3].x);
+          acc2[u & 3].y = fma(bv[u].y, ph, acc2[u & 3].y);
+        }
+      }
+      for (; P < fx.naux; P += 2) {
+        const double2 bv = *reinterpret_cast<const double2*>(b + (int64_t)P * nt);
+        acc2[0].x = fma(bv.x, phis[P], acc2[0].x);
+        acc2[0].y = fma(bv.y, phis[P], acc2[0].y);
+      }
+    }
+    const double sx = (acc2[0].x + acc2[1].x) + (acc2[2].x + acc2[3].x);
+    const double sy = (acc2[0].y + acc2[1].y) + (acc2[2].y + acc2[3].y);
+    if (half == 1 && m < H) { jbuf[2 * m] = sx; jbuf[2 * m + 1] = sy; }
+    __syncthreads();
+    if (half == 0 && m < H) {
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const int kk = 2 * m + w;
+        const double j2 = 2.0 * ((w ? sy : sx) + jbuf[kk]);
+        int mu, nu;
+        tri_row_col(kk, n, mu, nu);
+        const int64_t o1 = fx.off_C + (int64_t)mu * n + nu, o2 = fx.off_C + (int64_t)nu * n + mu;
+        double v1 = j2, v2 = j2;
+        if (F0) { v1 += F0[o1]; v2 += F0[o2]; }
+        if (htilde) { v1 += htilde[o1]; v2 += htilde[o2]; }
+        out[o1] = v1;
+        if (mu != nu) out[o2] = v2;
+      }
+    }
+    return;
+  }
   for (int kk = threadIdx.x; kk < nt; kk += blockDim.x) {
     const double* b = bx + kk;
     double a4[4] = {0.0, 0.0, 0.0, 0.0};
