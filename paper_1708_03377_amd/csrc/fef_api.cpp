@@ -157,7 +157,6 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
   p->naux_cls_off.assign(d->nclass + 1, 0);
   for (int c = 0; c < d->nclass; ++c) p->naux_cls_off[c + 1] = p->naux_cls_off[c] + d->naux[c];
   for (int k = 0; k < FEF_NPREC; ++k) p->geom[k] = geom_of(k, p->P0);
-  configure_split_kernels(p->geom[FEF_BF16X2].pw);
   (void)compute_units();
 
   // ---- fragment table -----------------------------------------------------

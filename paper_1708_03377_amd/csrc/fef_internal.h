@@ -251,7 +251,6 @@ void free_tiles(fef::TileSet& t);
 int compute_units();
 
 // One-time kernel attributes (dynamic LDS above 64 KB).
-void configure_split_kernels(int pw);
 
 // Workspace sizes (bytes).
 int64_t half_ws_bytes(const fef_plan_s& p, fef_prec prec);

@@ -23,7 +23,7 @@ namespace fef {
 //    from LDS and B_ov is written densely.  Small groups keep the LDS of a
 //    workgroup at 27 KB (nbf = 24), so five share a CU and the copies of
 //    some overlap the contractions of others.
-//  ht_pack_small_kernel: one workgroup per fragment: B_ov^x in LDS, W^x =
+//  ht_pack_small_kernel: one workgroup (eight waves) per fragment: B_ov^x in LDS, W^x =
 //    G^T B_ov^x on FP64 MFMA (accumulators stay in registers), and both
 //    pair-kernel operands of mode PREC written directly (FP16 scales from
 //    block-wide maxima).
@@ -90,8 +90,12 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
   }
 }
 
+// Eight waves per workgroup: with the 62 KB LDS buffer two workgroups share
+// a CU, and the extra waves hide the latency of the staging loads and of the
+// operand stores.
+constexpr int kPackThreads = 512;
 template <int PREC>
-__global__ __launch_bounds__(256) void ht_pack_small_kernel(
+__global__ __launch_bounds__(kPackThreads) void ht_pack_small_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
     const double* __restrict__ bov, const double* __restrict__ G,
     const int64_t* __restrict__ off_G, int P0, int kpad, int pw, double* __restrict__ w_out,
@@ -101,18 +105,18 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
   constexpr int kBld = kTile + 1;
   __shared__ double Bs[(kSmallP * kBld > kTile * (kSmallP + 1)) ? kSmallP * kBld
                                                                  : kTile * (kSmallP + 1)];
-  __shared__ double red[4];
+  __shared__ double red[kPackThreads / 64];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int ov = fi.ov, P = fi.naux;
   const int P4 = (P + 3) & ~3;
   // sixteen loads per thread in flight: positions outside B_ov load its first
   // element and store zero
-  for (int eb = threadIdx.x; eb < P4 * kTile; eb += 256 * 16) {
+  for (int eb = threadIdx.x; eb < P4 * kTile; eb += kPackThreads * 16) {
     double v16[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = eb + 256 * u;
+      const int e = eb + kPackThreads * u;
       const int pp = e / kTile, ia = e - (e / kTile) * kTile;
       const bool in = e < P4 * kTile && pp < P && ia < ov;
       const double x = bov[fi.off_bov + (in ? (int64_t)pp * ov + ia : 0)];
@@ -120,43 +124,45 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int e = eb + 256 * u;
+      const int e = eb + kPackThreads * u;
       if (e < P4 * kTile) Bs[(e / kTile) * kBld + (e - (e / kTile) * kTile)] = v16[u];
     }
   }
   __syncthreads();
   // W = G_{c,0}^T B_ov on FP64 MFMA (16x16x4): output tiles (q tile, ia
-  // tile) in q-major order, eight consecutive tiles per wave, so that a wave
-  // meets at most two q tiles.  The A operands (G^T, from the L2-resident
-  // coupling) of those two q tiles for every k step are loaded into
-  // registers first; B comes from LDS.
+  // tile) in q-major order, four consecutive tiles per wave (eight waves),
+  // so that a wave meets at most two q tiles.  The A operands (G^T, from
+  // the L2-resident coupling) of those two q tiles are loaded one k step
+  // ahead; B comes from LDS.
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const double* g = G + off_G[fi.cls];  // [P][P0]
   constexpr int kIT = kTile / 16;
   const int QT = (P0 + 15) >> 4, NT = QT * kIT;
-  constexpr int kTilesPerWave = (5 * kIT + 3) / 4;  // 8 (P0 <= 80)
+  constexpr int kTilesPerWave = (5 * kIT + kPackThreads / 64 - 1) / (kPackThreads / 64);
   constexpr int kSteps = kSmallP / 4;               // 20
   const int t0 = wave * kTilesPerWave;
   const int qa = t0 / kIT;  // first q tile of this wave; the other is qa + 1
-  double ga[2][kSteps];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int ks = 0; ks < kSteps; ++ks) {
-      const int pp = 4 * ks + lk, q = 16 * (qa + h) + li;
-      ga[h][ks] = (pp < P && q < P0) ? g[(int64_t)pp * P0 + q] : 0.0;
-    }
+  // A operands streamed one k step ahead (two L2 loads per step)
+  auto ga_load = [&](int ks, int h) {
+    const int pp = 4 * ks + lk, q = 16 * (qa + h) + li;
+    const bool in = pp < P && q < P0;
+    const double x = g[in ? (int64_t)pp * P0 + q : 0];
+    return in ? x : 0.0;
+  };
   d4 acc[kTilesPerWave];
 #pragma unroll
   for (int k = 0; k < kTilesPerWave; ++k) acc[k] = d4{0, 0, 0, 0};
   // every tile of the wave is contracted, also tiles past NT (their B
   // columns are in range and their A values finite; they are never
   // stored), so that a k step's eight LDS reads are issued before its MFMAs
+  double gc0 = ga_load(0, 0), gc1 = ga_load(0, 1);
 #pragma unroll
   for (int ks = 0; ks < kSteps; ++ks) {
     if (4 * ks >= P4) break;  // rows past P4 are not staged
     const int pp = 4 * ks + lk;
+    const double gn0 = ks + 1 < kSteps ? ga_load(ks + 1, 0) : 0.0;
+    const double gn1 = ks + 1 < kSteps ? ga_load(ks + 1, 1) : 0.0;
     double bv[kTilesPerWave];
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
@@ -166,9 +172,11 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
 #pragma unroll
     for (int k = 0; k < kTilesPerWave; ++k) {
       const int qt = (t0 + k) / kIT;
-      const double av = qt == qa ? ga[0][ks] : ga[1][ks];
+      const double av = qt == qa ? gc0 : gc1;
       acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[k], acc[k], 0, 0, 0);
     }
+    gc0 = gn0;
+    gc1 = gn1;
   }
   // element (r) of tile k: q = 16 qt + lk + 4 r, ia = 16 it + li
   double wmax = 0.0, bmax = 0.0;
@@ -187,7 +195,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
       }
     }
   }
-  for (int e = threadIdx.x; e < P * kTile; e += 256)
+  for (int e = threadIdx.x; e < P * kTile; e += kPackThreads)
     bmax = fmax(bmax, fabs(Bs[(e / kTile) * kBld + (e - (e / kTile) * kTile)]));
   const bool right = fi.off_R[PREC] >= 0;
   if (PREC == FEF_F64 || PREC == FEF_F32) {
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
         }
       }
     }
-    for (int e = threadIdx.x; e < kpad * kTile; e += 256) {
+    for (int e = threadIdx.x; e < kpad * kTile; e += kPackThreads) {
       const int k = e / kTile, m = e - (e / kTile) * kTile;
       if (k >= P0 || m >= ov) {
         L[(int64_t)k * fi.ld + m] = (T)0;
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
     const int nqc = pw / 8;
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     if (R)
-      for (int e = threadIdx.x; e < kTile * (nqc + 1); e += 256) {
+      for (int e = threadIdx.x; e < kTile * (nqc + 1); e += kPackThreads) {
         const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
         if (c == nqc) {
           *reinterpret_cast<u16x8*>(R + ia * xs + 2 * pw) = z8;
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(256) void ht_pack_small_kernel(
       }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTile * (nqc + 1); e += 256) {
+    for (int e = threadIdx.x; e < kTile * (nqc + 1); e += kPackThreads) {
       const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
       if (c == nqc) {
         *reinterpret_cast<u16x8*>(L + ia * xs + 2 * pw) = z8;
@@ -387,7 +395,7 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
                        dim3(grid.x, (p.max_naux_small + kSliceGroup - 1) / kSliceGroup),
                        dim3(256), lds, st, p.d_frag, p.d_ht_fused, B, C, bov, p.fuse_lds[0]);
 #define FEF_FUSED(M)                                                                              \
-  hipLaunchKernelGGL(ht_pack_small_kernel<M>, grid, dim3(256), 0, st, p.d_frag, p.d_ht_fused,     \
+  hipLaunchKernelGGL(ht_pack_small_kernel<M>, grid, dim3(kPackThreads), 0, st, p.d_frag, p.d_ht_fused,     \
                      bov, G, p.d_off_G, p.P0, kpad, pw, wo, o)
     switch (prec) {
       case FEF_F64: FEF_FUSED(FEF_F64); break;

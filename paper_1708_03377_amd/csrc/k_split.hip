@@ -333,6 +333,4 @@ hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double
   return hipGetLastError();
 }
 
-void configure_split_kernels(int pw) { (void)pw; }
-
 }  // namespace fef
