@@ -225,21 +225,24 @@ typedef struct {
   void* ws;               /* workspace, FEF_Q_SCF_WS_BYTES, FEF_Q_HALF_WS_BYTES
                              and FEF_Q_PAIR_WS_BYTES bytes are all needed */
   size_t ws_bytes;
-  double* Bp;             /* nullable: packed coefficient pool; when given,
-                             the pass packs B into it once and runs the
-                             SCF steps with fef_scf_step_packed */
+  double* Bp;             /* nullable: packed coefficient pool; when given
+                             (and niter > 0), the pass packs B into it inside
+                             its first SCF step and runs every step on it */
 } fef_pass_args;
 
 typedef struct fef_graph_s* fef_graph;
 
 /* Records one whole FEF pass -- clearing of flags, [reset of C, eps],
- * [packing of B], niter SCF steps
- * (fef_scf_step), the half transform and the pair energies in mode `prec`
- * -- into a HIP graph (stream capture on a private default-priority stream;
- * no allocation happens during replay).  Call outside any capture; the plan
- * and every buffer must outlive the graph.  Replays run the same kernels in
- * the same order as the eager calls, so results are bitwise identical to
- * them. */
+ * niter SCF steps (fef_scf_step, or with Bp: packing of B and
+ * fef_scf_step_packed), the half transform and the pair energies in mode
+ * `prec` -- into a HIP graph (stream capture on a private default-priority
+ * stream; no allocation happens during replay).  Call outside any capture;
+ * the plan and every buffer must outlive the graph.  With Bp the first
+ * step's moments kernel does the packing (reading B, writing Bp), and when
+ * D is given and every fragment has nbf <= 32 each step's eigensolver also
+ * leaves the next step's density, so later steps run no density kernel;
+ * the arithmetic and its order are those of the eager calls, so results
+ * (C, eps, D, E2) are bitwise identical to them. */
 fef_status fef_graph_create(fef_plan plan, const fef_pass_args* args, int32_t niter,
                             fef_prec prec, fef_graph* out);
 fef_status fef_graph_launch(fef_graph graph, void* stream);
