@@ -66,7 +66,7 @@ class Spec:
         return self.n_water + (1 if self.nucleobase else 0)
 
 
-CONFIGS = {
+WORKLOADS = {
     0: Spec(0, "water8-lattice-fp64", 8, lattice=2, cutoff=None, niter=3),
     1: Spec(1, "water1000-fp64", 1000, niter=10),
     2: Spec(2, "nucleobase1+water2000-batched", 2000, nucleobase=True,
@@ -332,7 +332,7 @@ def make_system(cfg, extra_seed: Sequence[int] = (), n_water: Optional[int] = No
     ``coupling_of`` takes the class coupling G from workload ``coupling_of``'s
     seed stream instead (boxes of the same fragment type share one coupling).
     """
-    spec = CONFIGS[cfg] if isinstance(cfg, int) else cfg
+    spec = WORKLOADS[cfg] if isinstance(cfg, int) else cfg
     if n_water is not None:
         spec = dataclasses.replace(spec, n_water=int(n_water))
     if cutoff != "cfg":

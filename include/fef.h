@@ -276,7 +276,7 @@ fef_status fef_pair_energies_masked(fef_plan plan, const void* ops, const double
  * rotation-invariant scalars of the Coulomb moments d^x = B^x : D^x (the
  * moments that carry the effective field of Eqs. wc and dp2e); the exact
  * pair kernel (fef_pair_energies_masked) evaluates every pair the surrogate
- * declines, so it stays both the fallback and the judge of the error.
+ * declines, so it is both the fallback and the reference for the error.
  *
  * Network: 17 -> 128 -> 128 -> 1 with SiLU after the two hidden layers.
  * Parameters of one member, packed in this order:
