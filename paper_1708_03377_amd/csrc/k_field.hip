@@ -288,6 +288,12 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
 // from B at their triangle positions and also written to Bp (the packing
 // of the first SCF step of a pass), in the same order as the packed
 // variant, so that Bp and d are bitwise those of packing then moments.
+// Blocks run fragment-major (the nqb Q blocks of a fragment are adjacent in
+// the 1-D grid), so the kernel streams the pool from its start to its end;
+// the fused field and J kernel (small fragments) walks the fragments
+// backwards and so starts on the slices this kernel read last, which the
+// memory-side cache still holds, and ends on the first ones, where the next
+// step's moments start again.
 constexpr int kMomQW = 8;
 template <bool kPack>
 __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
@@ -297,14 +303,16 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
                                                              const double* __restrict__ Dw,
                                                              double* __restrict__ dmom,
                                                              const double* __restrict__ Bfull,
-                                                             double* __restrict__ Bp_out) {
-  const FragInfo fi = frag[blockIdx.x];
-  const int q0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * kMomQW;
+                                                             double* __restrict__ Bp_out,
+                                                             int nqb) {
+  const int fx = blockIdx.x / nqb, qb = blockIdx.x - fx * nqb;
+  const FragInfo fi = frag[fx];
+  const int q0 = (qb * 4 + (threadIdx.x >> 6)) * kMomQW;
   if (q0 >= fi.naux) return;
   const int lane = threadIdx.x & 63;
   const int nq = min(kMomQW, fi.naux - q0);
   const int n = fi.nbf, nt = n * (n + 1) / 2, nn = n * n;
-  const int64_t ob = off_Bp[blockIdx.x] + (int64_t)q0 * nt, od = off_tri[blockIdx.x];
+  const int64_t ob = off_Bp[fx] + (int64_t)q0 * nt, od = off_tri[fx];
   const double* b = kPack ? nullptr : Bsrc + ob;
   const double* bf = kPack ? Bfull + fi.off_B + (int64_t)q0 * nn : nullptr;
   double* bo = kPack ? Bp_out + ob : nullptr;
@@ -436,7 +444,9 @@ __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
     const double* __restrict__ F0, const double* __restrict__ htilde, double* __restrict__ out) {
   extern __shared__ double part[];  // [NW][etot] per-wave partial e_c, then e; then phi^x
   const int NW = blockDim.x >> 6;
-  const int x = blockIdx.x;
+  // fragments in reverse order: the moments kernel before it streamed the
+  // slices forwards, so the last ones it read are the first ones read here
+  const int x = gridDim.x - 1 - blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int etot = naux_cls_off[nclass];
   for (int t = threadIdx.x; t < NW * etot; t += blockDim.x) part[t] = 0.0;
@@ -656,13 +666,14 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st,
                                const double* B_pack, double* Bp_out) {
-  const dim3 mgrid(p.nfrag, (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW));
+  const int nqb = (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW);
+  const dim3 mgrid((unsigned)((int64_t)p.nfrag * nqb));
   if (B_pack)
     hipLaunchKernelGGL(moments_packed_kernel<true>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
-                       p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out);
+                       p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out, nqb);
   else
     hipLaunchKernelGGL(moments_packed_kernel<false>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
-                       p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr);
+                       p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr, nqb);
   const int etot = p.naux_cls_off.back();
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   if (small_fragments(p)) {
