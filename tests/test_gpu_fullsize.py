@@ -6,7 +6,9 @@
   the oracle, on sampled pairs the oracle evaluates one by one from the GPU's
   final orbitals.
 * 1000 water fragments: one full SCF step of every fragment against the
-  oracle (orbital energies and densities), from the generated orbitals.
+  oracle (orbital energies and densities), from the generated orbitals; and
+  the captured pass's 10 SCF steps against the oracle and, bitwise, against
+  10 eager steps.
 * one 150-function nucleobase in 2000 waters: one SCF step (the nucleobase
   takes the large-matrix eigensolver) and the nucleobase's half transform.
 """
@@ -95,6 +97,47 @@ def test_scf_step_full_size():
     D = ctx.D.cpu().numpy()
     Dref = np.concatenate([d.ravel() for d in Dl])
     assert np.max(np.abs(D - Dref)) <= 1e-10
+
+
+def test_captured_pass_scf_full_size():
+    """1000 water fragments, the captured pass the benchmark replays (packing
+    inside the first step, the density carried by the eigensolver between
+    steps, the coefficient pool streamed forwards and backwards): after its
+    10 SCF steps the orbital energies, densities and the last density change
+    against 10 oracle steps from the generated orbitals, and bitwise against
+    10 eager steps on the packed coefficients."""
+    import paper_1708_03377_amd as lib
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = fefgen.make_system(1)
+    niter = s.spec.niter
+    ctx = lib.Context(s)
+    g = ctx.graph(niter, PREC["fp16x2"])
+    ctx.launch(g)
+    torch.cuda.synchronize()
+    assert int(ctx.flags.cpu()[0]) == 0
+    eps_g = ctx.eps.cpu().numpy().copy()
+    D_g = ctx.D.cpu().numpy().copy()
+    C_g = ctx.C.cpu().numpy().copy()
+    dmax_g = float(ctx.dD_max.cpu()[0])
+    del g
+    C, e = s.C.copy(), s.eps.copy()
+    for _ in range(niter):
+        C, e, Dl, odmax, ok = ofef.scf_step(s, C, e)
+    Dref = np.concatenate([d.ravel() for d in Dl])
+    err_e = np.max(np.abs(eps_g - e)); err_d = np.max(np.abs(D_g - Dref))
+    _say(f"captured pass vs oracle after {niter} steps: eps {err_e:.2e} D {err_d:.2e}"
+         f" dDmax {abs(dmax_g - odmax):.2e}")
+    assert err_e <= 1e-10 and err_d <= 1e-10
+    assert abs(dmax_g - odmax) <= 1e-10
+    ctx.reset_orbitals()
+    for _ in range(niter):
+        dmax_e = float(ctx.scf_step_packed().cpu()[0])
+    assert dmax_e == dmax_g
+    assert np.array_equal(ctx.eps.cpu().numpy(), eps_g)
+    assert np.array_equal(ctx.D.cpu().numpy(), D_g)
+    assert np.array_equal(ctx.C.cpu().numpy(), C_g)
 
 
 def test_nucleobase_scf_step_and_half_transform_full_size():
