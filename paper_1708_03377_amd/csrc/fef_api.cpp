@@ -483,11 +483,15 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   const ScfWs w = scf_ws(*p, ws);
   const double* Dold = Dprev ? Dprev : w.Dold;
   double* Dnew = Dout ? Dout : (D ? D : w.Dspare);
-  hipError_t e = Dprev ? launch_zero_scalar(dD_max, st)
-                       : launch_density(*p, C, w.Dold, Bp ? w.Dw : nullptr, dD_max, st);
+  // with a carried density the moments kernel clears the maximum that the
+  // eigensolver accumulates (no kernel of its own)
+  const bool clear_in_moments = Dprev && Bp && p->nfrag > 0;
+  hipError_t e = !Dprev ? launch_density(*p, C, w.Dold, Bp ? w.Dw : nullptr, dD_max, st)
+                 : clear_in_moments ? hipSuccess
+                                    : launch_zero_scalar(dD_max, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = Bp ? launch_field_packed(*p, Bp, G, w.Dw, F0, htilde, w.F, w.wd, w.wphi, st, B_pack,
-                                 Bp_out)
+                                 Bp_out, clear_in_moments ? dD_max : nullptr)
            : launch_field(*p, B, G, Dold, F0, htilde, w.F, w.wd, w.wphi, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, w.F, Dold, C, eps, Dnew, dD_max, flags, w.eigws, st,

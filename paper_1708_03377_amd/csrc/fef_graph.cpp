@@ -13,13 +13,20 @@ struct fef_graph_s {
 
 namespace fef {
 
-__global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = src[i];
+// Start of a replay, one kernel: the flags cleared and, with C0 given, the
+// generated orbitals and orbital energies copied back (one element per
+// thread, C then eps).
+__global__ void reset_kernel(int32_t* __restrict__ flags, const double* __restrict__ C0,
+                             double* __restrict__ C, int64_t nC, const double* __restrict__ eps0,
+                             double* __restrict__ eps, int64_t nEps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *flags = 0;
+  if (!C0) return;
+  if (i < nC)
+    C[i] = C0[i];
+  else if (i < nC + nEps)
+    eps[i - nC] = eps0[i - nC];
 }
-
-__global__ void zero_flags_kernel(int32_t* flags) { *flags = 0; }
 
 }  // namespace fef
 
@@ -48,10 +55,11 @@ fef_status fef_graph_create(fef_plan p, const fef_pass_args* a, int32_t niter, f
   if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) status = FEF_E_HIP;
   if (status == FEF_OK) {
     // each replay reports its own flags (a fill kernel, not a memset node)
-    hipLaunchKernelGGL(zero_flags_kernel, dim3(1), dim3(1), 0, st, a->flags);
-    if (a->C0 && p->nC > 0) {
-      hipLaunchKernelGGL(copy_kernel, dim3(256), dim3(256), 0, st, a->C0, a->C, p->nC);
-      hipLaunchKernelGGL(copy_kernel, dim3(64), dim3(256), 0, st, a->eps0, a->eps, p->nEps);
+    {
+      const int64_t n = a->C0 ? p->nC + p->nEps : 0;
+      const unsigned nb = (unsigned)std::max<int64_t>(1, (n + 255) / 256);
+      hipLaunchKernelGGL(reset_kernel, dim3(nb), dim3(256), 0, st, a->flags, a->C0, a->C, p->nC,
+                         a->eps0, a->eps, p->nEps);
     }
     // with a packed pool the first step packs B on the way (its moments
     // kernel reads B and writes Bp), the later steps read Bp; with small

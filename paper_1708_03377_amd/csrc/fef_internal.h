@@ -195,11 +195,13 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
 bool small_fragments(const fef_plan_s& p);
 hipError_t launch_zero_scalar(double* x, hipStream_t st);  // *x = 0 (a kernel, not a memset)
 // B_pack non-null: the moments kernel reads the slices from B and writes
-// their packed copy to Bp_out (= Bp) on the way (the first step of a pass)
+// their packed copy to Bp_out (= Bp) on the way (the first step of a pass).
+// zero_out non-null: the moments kernel also sets *zero_out = 0.
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st,
-                               const double* B_pack = nullptr, double* Bp_out = nullptr);
+                               const double* B_pack = nullptr, double* Bp_out = nullptr,
+                               double* zero_out = nullptr);
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st);
 // One packed SCF step that also writes the packed copy Bp of B (its moments

@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256) void pack_coefficients_kernel(const FragInfo* 
 // the fused field and J kernel (small fragments) walks the fragments
 // backwards and so starts on the slices this kernel read last, which the
 // memory-side cache still holds, and ends on the first ones, where the next
-// step's moments start again.
+// step's moments start again.  zero_out non-null: one thread clears it
+// (a maximum that a later kernel of the same step accumulates).
 constexpr int kMomQW = 8;
 template <bool kPack>
 __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __restrict__ frag,
@@ -304,7 +305,8 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
                                                              double* __restrict__ dmom,
                                                              const double* __restrict__ Bfull,
                                                              double* __restrict__ Bp_out,
-                                                             int nqb) {
+                                                             int nqb, double* __restrict__ zero_out) {
+  if (zero_out && blockIdx.x == 0 && threadIdx.x == 0) *zero_out = 0.0;
   const int fx = blockIdx.x / nqb, qb = blockIdx.x - fx * nqb;
   const FragInfo fi = frag[fx];
   const int q0 = (qb * 4 + (threadIdx.x >> 6)) * kMomQW;
@@ -665,15 +667,15 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st,
-                               const double* B_pack, double* Bp_out) {
+                               const double* B_pack, double* Bp_out, double* zero_out) {
   const int nqb = (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW);
   const dim3 mgrid((unsigned)((int64_t)p.nfrag * nqb));
   if (B_pack)
     hipLaunchKernelGGL(moments_packed_kernel<true>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
-                       p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out, nqb);
+                       p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out, nqb, zero_out);
   else
     hipLaunchKernelGGL(moments_packed_kernel<false>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
-                       p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr, nqb);
+                       p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr, nqb, zero_out);
   const int etot = p.naux_cls_off.back();
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   if (small_fragments(p)) {
