@@ -18,9 +18,11 @@ namespace fef {
 // Half transform of small fragments (nbf <= 32, one 96-wide tile, P_c <= 80)
 // in two kernels.
 //  ht_mo_small_kernel: one workgroup per (fragment, kSliceGroup factor
-//    slices): the slices of B^x are copied into LDS (global_load_lds, 16
-//    bytes per lane), then X = C_occ^T B_P and B_ov = X C_vir are formed
-//    from LDS and B_ov is written densely.  Small groups keep the LDS of a
+//    slices), fragment-major (the nsg slice groups of a fragment are
+//    adjacent in the 1-D grid, so B is streamed in order and the
+//    fragment's C is reused from cache): the slices of B^x are copied into
+//    LDS (global_load_lds, 16 bytes per lane), then X = C_occ^T B_P and
+//    B_ov = X C_vir are formed from LDS and B_ov is written densely.  Small groups keep the LDS of a
 //    workgroup at 27 KB (nbf = 24), so five share a CU and the copies of
 //    some overlap the contractions of others.
 //  ht_pack_small_kernel: one workgroup (eight waves) per fragment: B_ov^x in LDS, W^x =
@@ -33,14 +35,16 @@ __global__ __launch_bounds__(256) void ht_mo_small_kernel(const FragInfo* __rest
                                                           const int32_t* __restrict__ list,
                                                           const double* __restrict__ B,
                                                           const double* __restrict__ C,
-                                                          double* __restrict__ bov, int max_nn) {
+                                                          double* __restrict__ bov, int max_nn,
+                                                          int nsg) {
   extern __shared__ double sm[];
   const int cs_ld = (max_nn + 1) & ~1;              // keeps Bst 16-byte aligned
   double* Cs = sm;                                  // [nbf][nbf]
   double* Bst = sm + cs_ld;                         // [kSliceGroup][nbf][nbf]
   double* Xs = sm + cs_ld + kSliceGroup * max_nn;   // [kSliceGroup][nocc][nbf]
-  const FragInfo fi = frag[list[blockIdx.x]];
-  const int p0 = blockIdx.y * kSliceGroup;
+  const int fx = blockIdx.x / nsg, sg = blockIdx.x - fx * nsg;
+  const FragInfo fi = frag[list[fx]];
+  const int p0 = sg * kSliceGroup;
   if (p0 >= fi.naux) return;
   const int np = min(kSliceGroup, fi.naux - p0);
   const int n = fi.nbf, o = fi.nocc, v = fi.nvir, ov = fi.ov, nn = n * n;
@@ -391,9 +395,9 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
     const size_t lds = (size_t)(((p.fuse_lds[0] + 1) & ~1) + kSliceGroup * p.fuse_lds[0] +
                                 kSliceGroup * p.fuse_lds[1]) *
                        sizeof(double);
-    hipLaunchKernelGGL(ht_mo_small_kernel,
-                       dim3(grid.x, (p.max_naux_small + kSliceGroup - 1) / kSliceGroup),
-                       dim3(256), lds, st, p.d_frag, p.d_ht_fused, B, C, bov, p.fuse_lds[0]);
+    const int nsg = (p.max_naux_small + kSliceGroup - 1) / kSliceGroup;
+    hipLaunchKernelGGL(ht_mo_small_kernel, dim3((unsigned)((int64_t)grid.x * nsg)),
+                       dim3(256), lds, st, p.d_frag, p.d_ht_fused, B, C, bov, p.fuse_lds[0], nsg);
 #define FEF_FUSED(M)                                                                              \
   hipLaunchKernelGGL(ht_pack_small_kernel<M>, grid, dim3(kPackThreads), 0, st, p.d_frag, p.d_ht_fused,     \
                      bov, G, p.d_off_G, p.P0, kpad, pw, wo, o)
