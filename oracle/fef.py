@@ -90,31 +90,6 @@ def orbital_gaps(eps: np.ndarray, nocc: int) -> np.ndarray:
     return eps[:nocc, None] - eps[None, nocc:]
 
 
-def pair_energy_from_integrals(V: np.ndarray, eps_x: np.ndarray, eps_y: np.ndarray,
-                               nocc_x: int, nocc_y: int) -> float:
-    """E2_xy = 4 sum_{ijab} (ia|jb) t^{ab}_{ij},  t = (ia|jb)/(e_i+e_j-e_a-e_b).
-
-    Eq. ED2 with the first-order amplitudes of Eq. dimDoubles (diagonal F^[0],
-    canonical orbitals); factor 4 from the closed-shell spin sum.
-    """
-    dx = orbital_gaps(eps_x, nocc_x)
-    dy = orbital_gaps(eps_y, nocc_y)
-    D = dx[:, :, None, None] + dy[None, None, :, :]
-    t = V / D
-    return float(4.0 * np.sum(V * t))
-
-
-def pair_energy(sys, x: int, y: int, s: float, C_pool=None, eps_pool=None) -> float:
-    """E2 for one fragment pair from the system's pools (plain definition)."""
-    Cx = sys.C_of(x, C_pool); Cy = sys.C_of(y, C_pool)
-    ex = sys.eps_of(x, eps_pool); ey = sys.eps_of(y, eps_pool)
-    ox = int(sys.nocc[x]); oy = int(sys.nocc[y])
-    Bx = half_transform(sys.B_of(x), Cx, ox)
-    By = half_transform(sys.B_of(y), Cy, oy)
-    V = pair_integrals(Bx, By, coupling(sys, x, y, s))
-    return pair_energy_from_integrals(V, ex, ey, ox, oy)
-
-
 def pair_energies(sys, C_pool=None, eps_pool=None, pairs=None):
     """E2_xy for every listed pair and E_D2 = sum over the unordered pairs.
 
