@@ -139,11 +139,18 @@ fef_status fef_plan_query(fef_plan plan, fef_query what, fef_prec prec,
  *        all.
  *   yc : y tiles per work item of the persistent queue (1..4096).
  * Rebuilds device tables (allocates): call outside graph capture, with no
- * pair-energy call of this plan in flight.  The autotuner uses this. */
+ * pair-energy call of this plan in flight.  A captured pass of this mode
+ * that is still alive keeps the tables it was captured with (they are freed
+ * with the plan), so it replays with its old tiling.  The autotuner uses
+ * this. */
 fef_status fef_plan_set_tiles(fef_plan plan, fef_prec prec, int32_t xb, int32_t yc);
 fef_status fef_plan_get_tiles(fef_plan plan, fef_prec prec, int32_t* xb, int32_t* yc);
 
-/* Half transform (the x-side half of the four-index AO->MO transform).
+/* Half transform (the x-side half of the four-index AO->MO transform of the
+ * inter-fragment integrals v^{pq}_{rs} of the dimer Hamiltonian, Eq. NHxy,
+ * with the MO coefficients C_{mu p} of Sec. II.A):
+ *   B^x_ov[P][ia] = sum_{mu nu} C^x_{mu i} B^x[P][mu][nu] C^x_{nu a},
+ *   W^x = G_{c(x),0}^T B^x_ov.
  *   B, C, G : input pools (device).
  *   Bov, W  : optional dense FP64 outputs (device); both or neither may
  *             be NULL.

@@ -24,6 +24,7 @@ hipError_t upload(T** dst, const std::vector<T>& src) {
 void free_plan(fef_plan_s* p) {
   if (!p) return;
   for (auto& t : p->tiles) free_tiles(t);
+  for (auto& t : p->retired_tiles) free_tiles(t);
   void* ptrs[] = {p->d_frag, p->d_pair, p->d_slot_pair, p->d_ht, p->d_ht_fused, p->d_ht_generic,
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
@@ -40,7 +41,7 @@ OpsGeom geom_of(int prec, int P0) {
     case FEF_F32: return {4, (int)round_up(P0, 4), 0};
     default: {
       const int pw = (int)round_up(P0, 8);
-      return {2, (int)round_up(3 * (int64_t)pw, 32), pw};
+      return {2, 32 * (split_chain_a(pw) + split_chain_b(pw)), pw};
     }
   }
 }
@@ -98,8 +99,7 @@ int64_t surr_ws_bytes(const fef_plan_s& p) {
   return std::max(modes, inv);
 }
 int64_t scf_ws_bytes(const fef_plan_s& p) {
-  const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
-  const int64_t large = 2 * (int64_t)p.eig_large.size() * slot;
+  const int64_t large = (int64_t)p.eig_large.size() * eig_large_slot(p.eig_large_max_nbf);
   // Dold, F, Dnew [nC] each, the eigensolver slots, the weighted packed
   // density [nTri]
   int64_t n = 3 * std::max<int64_t>(p.nC, 1) + large + std::max<int64_t>(p.nTri, 1);
@@ -459,8 +459,7 @@ static ScfWs scf_ws(const fef_plan_s& p, void* ws) {
   w.F = w.Dold + std::max<int64_t>(p.nC, 1);
   w.Dspare = w.F + std::max<int64_t>(p.nC, 1);
   w.eigws = w.F + 2 * std::max<int64_t>(p.nC, 1);
-  const int64_t slot = (int64_t)(p.eig_large_max_nbf + 1) * (p.eig_large_max_nbf + 1);
-  w.Dw = w.eigws + 2 * (int64_t)p.eig_large.size() * slot;
+  w.Dw = w.eigws + (int64_t)p.eig_large.size() * eig_large_slot(p.eig_large_max_nbf);
   return w;
 }
 

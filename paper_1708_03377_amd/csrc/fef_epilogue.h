@@ -52,17 +52,9 @@ __device__ inline double weighted_tiles(const AccT (&acc)[TI][TJ], const double*
 // inside FP32: the FP16 operand scales bound |v| by 2^28 K, and |d| is an
 // orbital-energy gap.  The column gaps gy may be stored in FP32 or FP64
 // (converted on load).
-template <int TI, int TJ, typename GyT>
-__device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float* gx,
-                                            const GyT* gy, int lane) {
-  const int li = lane & 15, lk = lane >> 4;
-  float dx[TI][4], dy[TJ];
-#pragma unroll
-  for (int i = 0; i < TI; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + 4 * lk + r];
-#pragma unroll
-  for (int j = 0; j < TJ; ++j) dy[j] = (float)gy[16 * j + li];
+template <int TI, int TJ>
+__device__ inline double weighted_tiles_f32_regs(const f4 (&acc)[TI][TJ], const float (&dx)[TI][4],
+                                                 const float (&dy)[TJ]) {
   float sum = 0.0f;
 #pragma unroll
   for (int i = 0; i < TI; ++i)
@@ -82,6 +74,22 @@ __device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float
       sum += fmaf(r, fmaf(-den, q, num), q);
     }
   return (double)sum;
+}
+
+// The same with the row gaps gx and column gaps gy read from memory (gy in
+// FP32 or FP64, converted on load).
+template <int TI, int TJ, typename GyT>
+__device__ inline double weighted_tiles_f32(const f4 (&acc)[TI][TJ], const float* gx,
+                                            const GyT* gy, int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  float dx[TI][4], dy[TJ];
+#pragma unroll
+  for (int i = 0; i < TI; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + 4 * lk + r];
+#pragma unroll
+  for (int j = 0; j < TJ; ++j) dy[j] = (float)gy[16 * j + li];
+  return weighted_tiles_f32_regs<TI, TJ>(acc, dx, dy);
 }
 
 }  // namespace fef

@@ -9,6 +9,8 @@
 struct fef_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  fef_plan plan = nullptr;  // its tile tables of mode `prec` are baked in
+  int prec = 0;
 };
 
 namespace fef {
@@ -95,6 +97,9 @@ fef_status fef_graph_create(fef_plan p, const fef_pass_args* a, int32_t niter, f
     delete g;
     return status;
   }
+  g->plan = p;
+  g->prec = (int)prec;
+  ++p->graphs_live[prec];
   *out = g;
   return FEF_OK;
 }
@@ -109,6 +114,7 @@ fef_status fef_graph_destroy(fef_graph g) {
   if (!g) return FEF_E_ARG;
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->plan) --g->plan->graphs_live[g->prec];
   delete g;
   return FEF_OK;
 }

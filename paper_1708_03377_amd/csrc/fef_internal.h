@@ -72,8 +72,29 @@ struct HtTask {
 //   FP64 / FP32: operand stored [kpad][ld], k-major, kpad = round_up(P0, 4).
 //   split modes: operand stored [ld][2 * pw + 8] (row = ia; hi plane, lo
 //   plane, pw = round_up(P0, 8), then 8 zeros so that rows staged in LDS sit
-//   12 banks apart); the contraction runs over the concatenated axis of
-//   length kpad = round_up(3 * pw, 32).
+//   12 banks apart); the leading product runs over round_up(pw, 32) and the
+//   two cross products over round_up(2 pw, 32) contraction indices, kpad
+//   is their sum.
+// Split modes: MFMA chunks (32 contraction indices each) of the leading
+// product hi.hi (chain A) and of the two cross products (chain B) for a
+// plane width pw.
+__host__ __device__ constexpr int split_chain_a(int pw) { return (pw + 31) / 32; }
+__host__ __device__ constexpr int split_chain_b(int pw) { return (2 * pw + 31) / 32; }
+
+// Eigensolver workspace (doubles) per fragment with nbf > 48, for the
+// largest such nbf: the Jacobi path keeps V^T and a product matrix
+// (2 (n + 1)^2), the tridiagonal path T (three vectors), the packed
+// reflectors, the eigenvectors of T (rows padded to n + 64 columns) and six
+// vectors of elimination factors per eigenvalue.
+__host__ __device__ inline int64_t eig_large_slot(int nmax) {
+  const int64_t jac = 2 * (int64_t)(nmax + 1) * (nmax + 1);
+  const int64_t tri = 3 * (int64_t)nmax + (int64_t)nmax * (nmax + 1) / 2 +
+                      (int64_t)nmax * (nmax + 64) + 6 * (int64_t)nmax * nmax;
+  return jac > tri ? jac : tri;
+}
+// Largest nbf of the tridiagonal (Householder) eigensolver.
+constexpr int kTriMax = 152;
+
 struct OpsGeom {
   int elem_bytes;   // bytes per stored element
   int kpad;         // padded contraction length
@@ -139,6 +160,10 @@ struct fef_plan_s {
   std::vector<fef::PairInfo> pairs;   // host copy (oriented)
   std::vector<int32_t> rank;          // locality order position per fragment
   fef::TileSet tiles[FEF_NPREC];
+  // captured passes alive per mode: while any holds a mode's tile tables,
+  // a retune keeps the superseded tables (freed with the plan)
+  int32_t graphs_live[FEF_NPREC] = {0, 0, 0, 0};
+  std::vector<fef::TileSet> retired_tiles;
   fef::HtTask* d_ht = nullptr;
   int64_t* d_off_G = nullptr;
   int32_t* d_naux_cls_off = nullptr;
@@ -186,6 +211,9 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* C, double* eps, double* Dnew, double* dD_max,
                        int32_t* flags, double* ws_eig, hipStream_t st, double* Dw = nullptr);
+hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* Dold, double* C,
+                           double* eps, double* Dnew, double* dD_max, int32_t* flags,
+                           double* ws_eig, hipStream_t st);
 hipError_t launch_eigh_one(const FragInfo* d_fi, const int32_t* d_list, int n, const double* F,
                            const double* Dold, double* C, double* eps, double* Dnew,
                            double* dmax, int32_t* flags, double* ws_eig, hipStream_t st);

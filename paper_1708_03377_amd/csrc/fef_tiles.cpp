@@ -244,7 +244,10 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
   if (e == hipSuccess) e = upload_vec(&t.d_xblocks, blocks);
   if (e == hipSuccess) e = upload_vec(&t.d_grp_off, grp_off);
   if (e != hipSuccess) { free_tiles(t); return e; }
-  free_tiles(p.tiles[prec]);
+  if (p.graphs_live[prec] > 0)
+    p.retired_tiles.push_back(p.tiles[prec]);  // a captured pass still reads them
+  else
+    free_tiles(p.tiles[prec]);
   p.tiles[prec] = t;
   return hipSuccess;
 }

@@ -609,7 +609,7 @@ __global__ __launch_bounds__(1024) void eigh_large_kernel(
   int* rank = reinterpret_cast<int*>(lam + m);
   int* occ = rank + m;
   const size_t slot = (size_t)(max_n + 1) * (max_n + 1);
-  double* Vt = ws_eig + (size_t)blockIdx.x * 2 * slot;  // [m][m]
+  double* Vt = ws_eig + (size_t)blockIdx.x * eig_large_slot(max_n);  // [m][m]
   double* T = Vt + slot;                                 // [n][n]
   const double* Fx = F + fi.off_C;
   const double* Cx = C + fi.off_C;
@@ -808,7 +808,10 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        st, p.d_frag, p.d_eig_mid, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig,
                        nmax);
   }
-  if (!p.eig_large.empty() && p.eig_large_max_nbf <= kLargeMax) {
+  if (!p.eig_large.empty() && p.eig_large_max_nbf <= kTriMax) {
+    hipError_t e = launch_eigh_tri(p, F, Dold, C, eps, Dnew, dD_max, flags, ws_eig, st);
+    if (e != hipSuccess) return e;
+  } else if (!p.eig_large.empty() && p.eig_large_max_nbf <= kLargeMax) {
     const int nmax = p.eig_large_max_nbf;
     static bool configured = false;
     if (!configured) {

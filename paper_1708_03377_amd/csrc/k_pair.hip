@@ -68,6 +68,14 @@ __global__ __launch_bounds__(256 * XB) void pair_plain_kernel(
   const int unit = wave >> 2, sub = wave & 3;
   const int r0 = (sub >> 1) * 48, c0 = (sub & 1) * 48;
   const int tile_ch = kpad * kRowCh;
+  // The MFMA loop reads k rows up to 4 KS - 1 of both buffers, the copies
+  // fill rows below kpad only: rows kpad .. 4 KS - 1 are zeroed once here
+  // (the barrier after the first queue pull orders this before any read),
+  // so a stale non-finite value can never meet the zero x operand there.
+  for (int e = kpad * kTile + (int)threadIdx.x; e < 4 * KS * kTile; e += NT) {
+    YsA[e] = (T)0;
+    YsB[e] = (T)0;
+  }
   // copy of entry E's y tile ([kpad][96] of a [kpad][ld_y] operand) and gaps
   auto issue = [&](int E, T* Y, double* G) {
     const int64_t yld = entries[E].ld_y;

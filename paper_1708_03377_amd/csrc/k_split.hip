@@ -4,18 +4,22 @@
 // Each operand value x is split as x = hi + lo with hi = rn(x), lo = rn(x - hi)
 // (rn = round to nearest even in the 16-bit format).  The product keeps the
 // three leading terms
-//     x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y
+//     x y ~ hi_x hi_y + (hi_x lo_y + lo_x hi_y)
 // and drops lo_x lo_y.  Each fragment stores one row per ia: [hi | lo], each
-// plane pw = round_up(P0, 8) wide.  The three products run as ONE contraction
-// over a concatenated axis of length 3 pw (padded to a multiple of 32):
-//     x (left)  segments: hi(W^x), hi(W^x), lo(W^x)
-//     y (right) segments: hi(B^y), lo(B^y), hi(B^y)
-// so a single 16x16x32 MFMA chain computes all three; pw is a multiple of 8,
-// so the 8 contraction indices a lane feeds one MFMA never straddle two
-// segments.  FP16 operands carry a
-// per-fragment power-of-two scale that places each operand's largest value
-// in [2^13, 2^14), keeping lo parts out of the subnormal range; the scales
-// are undone exactly in FP64.
+// plane pw = round_up(P0, 8) wide, then 8 zeros.  The leading product and
+// the two cross products run as two MFMA chains with separate FP32
+// accumulators, added once per element in the epilogue:
+//     chain A (NA chunks of 32): x hi . y hi,
+//     chain B (NB chunks of 32): x [hi | lo] . y [lo | hi],
+// padded with the row's zero tail.  Within one MFMA instruction the
+// hardware drops the low bits of addends far below the largest one; a cross
+// product is about 2^-9 (BF16) or 2^-12 (FP16, relative to the scaled
+// operand) of a leading product, so sharing an accumulator with the leading
+// products would truncate the cross terms systematically.  pw is a multiple
+// of 8, so the 8 contraction indices a lane feeds one MFMA never straddle
+// two planes.  FP16 operands carry a per-fragment power-of-two scale that
+// places each operand's largest value in [2^13, 2^14), keeping lo parts out
+// of the subnormal range; the scales are undone exactly in FP64.
 #include <algorithm>
 
 #include "fef_internal.h"
@@ -125,6 +129,20 @@ hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const doubl
   return hipGetLastError();
 }
 
+// Waits until at most n (0..15, uniform across the wave) of this wave's
+// vector memory operations are outstanding; the other counters are not
+// waited for.  gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8.
+__device__ inline void wait_vm_upto(int n) {
+#define FEF_VM(N) case N: __builtin_amdgcn_s_waitcnt((N) | (7 << 4) | (15 << 8)); break;
+  switch (n) {
+    FEF_VM(0) FEF_VM(1) FEF_VM(2) FEF_VM(3) FEF_VM(4) FEF_VM(5) FEF_VM(6) FEF_VM(7)
+    FEF_VM(8) FEF_VM(9) FEF_VM(10) FEF_VM(11) FEF_VM(12) FEF_VM(13) FEF_VM(14) FEF_VM(15)
+    default: __builtin_amdgcn_s_waitcnt(0);
+  }
+#undef FEF_VM
+}
+
 template <bool kFp16>
 __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
   if (kFp16)
@@ -150,7 +168,7 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
 // contraction indices 8 (lane / 16) .. +7.
 constexpr int kXsMax = 2 * 80 + 8;  // row stride bound (pw <= 80)
 
-template <bool kFp16, int XB, int NCH>
+template <bool kFp16, int XB, int NA, int NB>
 __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
@@ -176,16 +194,18 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
   const int xs = 2 * pw + 8;           // row stride (16-bit elements) in HBM and LDS
   const int tile_ch = kTile * xs / 8;  // 16-byte chunks per tile
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-  // this lane's contraction segments: x reads hi, hi, lo; y reads hi, lo,
-  // hi; indices past 3 pw read the 8 zeros that end every stored row
-  int xoff[NCH], yoff[NCH];
+  // this lane's contraction offsets in a stored row.  Chain B (cross
+  // products) reads x [hi | lo] at kb = 32 m + 8 (lane / 16) against y
+  // [lo | hi]; chain A reuses x chunk c < NA (hi wherever kb < pw, and
+  // kb < pw covers all of the hi plane) against y hi, zero elsewhere.
+  // Offsets past a chain's length read the 8 zeros that end every row.
+  int xoff[NB], yoffB[NB], yoffA[NA];
 #pragma unroll
-  for (int c = 0; c < NCH; ++c) {
-    const int kk = 32 * c + 8 * lk;
-    const int seg = kk / pw;
-    const int off = kk - seg * pw;
-    xoff[c] = seg < 3 ? (seg == 2 ? pw : 0) + off : 2 * pw;
-    yoff[c] = seg < 3 ? (seg == 1 ? pw : 0) + off : 2 * pw;
+  for (int m = 0; m < NB; ++m) {
+    const int kb = 32 * m + 8 * lk;
+    xoff[m] = kb < 2 * pw ? kb : 2 * pw;
+    yoffB[m] = kb < pw ? pw + kb : (kb < 2 * pw ? kb - pw : 2 * pw);
+    if (m < NA) yoffA[m] = kb < pw ? kb : 2 * pw;
   }
   // copy of entry E's y tile and gaps into the LDS buffers (Y, G): wave w
   // moves the 1 KB pieces w, w + NW, ...; the last wave also moves the gaps
@@ -213,20 +233,20 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
     const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
-    u16x8 xa[TI][NCH];
+    u16x8 xa[TI][NB];
     if (fxi >= 0) {
       const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
                           (int64_t)(mt * kTile + r0 + li) * xs;
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c)
+        for (int c = 0; c < NB; ++c)
           xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
     } else {
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) xa[i][c] = zero;
+        for (int c = 0; c < NB; ++c) xa[i][c] = zero;
     }
     for (int t = threadIdx.x; t < XB * kTile; t += NT) {
       const int u = t / kTile, m = t - (t / kTile) * kTile;
@@ -260,17 +280,45 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
           for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int j = 0; j < TJP; ++j) acc[i][j] = f4{0, 0, 0, 0};
+#ifdef FEF_SPLIT_SEPARATE
+          f4 accB[TI][TJP];
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJP; ++j) accB[i][j] = f4{0, 0, 0, 0};
+#else
+          f4 (&accB)[TI][TJP] = acc;
+#endif
+          // chain B: the cross products, in chunks of their own
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
             u16x8 b[TJP];
 #pragma unroll
             for (int j = 0; j < TJP; ++j)
-              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoff[c]);
+              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoffB[c]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+              for (int j = 0; j < TJP; ++j) accB[i][j] = mma16<kFp16>(xa[i][c], b[j], accB[i][j]);
+          }
+          // chain A: the leading products
+#pragma unroll
+          for (int c = 0; c < NA; ++c) {
+            u16x8 b[TJP];
+#pragma unroll
+            for (int j = 0; j < TJP; ++j)
+              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoffA[c]);
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
               for (int j = 0; j < TJP; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
           }
+#ifdef FEF_SPLIT_SEPARATE
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJP; ++j) acc[i][j] += accB[i][j];
+#endif
           part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0, Gc + 16 * jh * TJP,
                                              lane);
         }
@@ -292,41 +340,240 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
 }
 
 
-template <bool F16, int XB>
-static void launch_split_nch(const fef_plan_s& p, int nch, dim3 grid, hipStream_t st,
-                             const char* o, int prec, int pw, const double* gap,
-                             const Entry* entries, const WorkItem* items, double* partial,
-                             int32_t* head) {
+// Ping-pong split pair kernel: two x units per workgroup, eight waves, one
+// workgroup per CU.  Waves w and w + 4 share a SIMD and hold the same 48 x
+// rows of one unit (wave w: columns 0-47 of the streamed y tile, wave w + 4:
+// columns 48-95), 3 x 3 MFMA tiles each.  The two groups of four waves run
+// half a step apart: in every phase one group contracts an entry on MFMA
+// while the other weights the previous entry's accumulators on the VALU, so
+// on each SIMD the matrix chain of one wave overlaps the FP32 epilogue of
+// the other by construction.  A phase ends at a workgroup barrier:
+//   phase 2e    : group A contracts entry e,  group B weights entry e - 1
+//   phase 2e + 1: group A weights entry e,    group B contracts entry e
+// The y tiles rotate through three LDS buffers: the copy of entry e + 2 is
+// issued at phase 2e into the buffer entry e - 1 left, and entry e + 1's
+// copy (issued two phases earlier) is waited for at the end of phase 2e + 1
+// while the newest copy stays in flight, so a copy has three phases to land.
+// Each wave takes its column gaps into registers while it contracts, so an
+// epilogue never reads a buffer being refilled.  Each wave leaves its weighted sum in LDS; once
+// both groups have weighted entry e, one lane per unit adds the four wave
+// sums in a fixed order into the entry's partial slot.
+template <bool kFp16, int NA, int NB>
+__global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
+    const FragInfo* __restrict__ frag, const XBlock* __restrict__ xblocks,
+    const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
+    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops,
+    int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
+  constexpr int XB = 2, NW = 8, NT = 512, NBUF = 3;
+  __shared__ __align__(16) uint16_t Ys[NBUF][kTile * kXsMax];
+  __shared__ __align__(16) double Gy[NBUF][kTile];
+  __shared__ float Gx[XB * kTile];
+  __shared__ double red[2][NW];
+  __shared__ int32_t s_item;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int grp = wave >> 2, unit = (wave >> 1) & 1;
+  const int r0 = 48 * (wave & 1), c0 = 48 * grp;
+  const double* hdr = reinterpret_cast<const double*>(ops);
+  const int xs = 2 * pw + 8;
+  const int tile_ch = kTile * xs / 8;
+  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  int xoff[NB], yoffB[NB], yoffA[NA];
+#pragma unroll
+  for (int m = 0; m < NB; ++m) {
+    const int kb = 32 * m + 8 * lk;
+    xoff[m] = kb < 2 * pw ? kb : 2 * pw;
+    yoffB[m] = kb < pw ? pw + kb : (kb < 2 * pw ? kb - pw : 2 * pw);
+    if (m < NA) yoffA[m] = kb < pw ? kb : 2 * pw;
+  }
+  // global_load_lds operations one copy puts in flight in this wave
+  int nload = wave == NW - 1 ? 1 : 0;
+  for (int g = wave; g * 64 < tile_ch; g += NW) ++nload;
+  auto issue = [&](int E, uint16_t* Y, double* G) {
+    const char* src = ops + entries[E].off_R;
+    for (int g = wave; g * 64 < tile_ch; g += NW) {
+      const int c = g * 64 + lane;
+      if (c < tile_ch)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 16 * (int64_t)c),
+                                         (lds_void_t*)(Y + g * 512), 16, 0, 0);
+    }
+    if (wave == NW - 1 && lane < kTile / 2)
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gap + entries[E].off_gap + 2 * lane),
+                                       (lds_void_t*)(G), 16, 0, 0);
+  };
+  for (;;) {
+    if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
+    __syncthreads();
+    const int32_t it = s_item;
+    __syncthreads();
+    if (it < 0 || it >= nitems) break;
+    const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
+    if (ne == 0) continue;  // an item emptied by a pair mask
+    issue(e0, Ys[0], Gy[0]);
+    if (ne > 1) issue(e0 + 1, Ys[1], Gy[1]);
+    const int fxi = xblocks[xbid].f[unit];
+    const int mt = xblocks[xbid].mt[unit];
+    u16x8 xa[3][NB];
+    if (fxi >= 0) {
+      const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
+                          (int64_t)(mt * kTile + r0 + li) * xs;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) xa[i][c] = zero;
+    }
+    for (int t = threadIdx.x; t < XB * kTile; t += NT) {
+      const int u = t / kTile, m = t - (t / kTile) * kTile;
+      const int f = xblocks[xbid].f[u];
+      Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // partial slot of entry E for unit u, from the four wave sums of
+    // the unit in a fixed order
+    auto finish = [&](int el, int u) {
+      const int E = e0 + el;
+      const int slot = entries[E].slot[u];
+      if (slot < 0) return;
+      const double s = entries[E].s[u];
+      const double sc = hdr[2 * xblocks[xbid].f[u]] * hdr[2 * entries[E].y + 1];
+      const double* r = red[el & 1];
+      partial[slot] = 4.0 * s * s * sc * sc *
+                      ((r[2 * u] + r[2 * u + 1]) + (r[4 + 2 * u] + r[4 + 2 * u + 1]));
+    };
+    f4 acc[3][3];
+    float dy[3];
+    for (int t = 0; t <= 2 * ne; ++t) {
+      if (t >= 3 && (t & 1) && threadIdx.x < XB) finish((t - 3) >> 1, threadIdx.x);
+      const int en = (t >> 1) + 2;  // the copy issued at this even phase
+      if (!(t & 1) && en < ne) issue(e0 + en, Ys[en % NBUF], Gy[en % NBUF]);
+      if ((grp == 0) == !(t & 1)) {
+        // contraction phase
+        const int el = grp == 0 ? (t >> 1) : ((t - 1) >> 1);
+        if (el < ne && entries[e0 + el].slot[unit] >= 0) {
+          const uint16_t* Yb = Ys[el % NBUF] + (c0 + li) * xs;
+          const double* Gc = Gy[el % NBUF] + c0 + li;
+#pragma unroll
+          for (int j = 0; j < 3; ++j) dy[j] = (float)Gc[16 * j];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) acc[i][j] = f4{0, 0, 0, 0};
+          // the cross products first, in chunks of their own; then the
+          // leading products continue the same accumulators
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+            u16x8 b[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoffB[c]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+          }
+#pragma unroll
+          for (int c = 0; c < NA; ++c) {
+            u16x8 b[3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoffA[c]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int j = 0; j < 3; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+          }
+        }
+      } else {
+        // weighting phase
+        const int el = grp == 0 ? ((t - 1) >> 1) : ((t >> 1) - 1);
+        if (el >= 0) {
+          double mine = 0.0;
+          if (entries[e0 + el].slot[unit] >= 0) {
+            float dx[3][4];
+            const float* gx = Gx + unit * kTile + r0 + 4 * lk;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + r];
+            mine = wave_sum_dpp(weighted_tiles_f32_regs<3, 3>(acc, dx, dy));
+          }
+          if (lane == 0) red[el & 1][wave] = mine;
+        }
+      }
+      // at the end of an odd phase 2e + 1 the copy of entry e + 1 has landed
+      // (this wave's part; after the barrier, every wave's part); the copy of
+      // entry e + 2, issued last, may stay in flight
+      if (t & 1) {
+        if ((t >> 1) + 2 < ne)
+          wait_vm_upto(nload);
+        else
+          __builtin_amdgcn_s_waitcnt(0);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < XB) finish(ne - 1, threadIdx.x);
+  }
+}
+
+template <bool F16>
+static void launch_split_pp(const fef_plan_s& p, int na, int nb, dim3 grid, hipStream_t st,
+                            const char* o, int prec, int pw, const double* gap,
+                            const Entry* entries, const WorkItem* items, double* partial,
+                            int32_t* head) {
   const TileSet& t = p.tiles[prec];
-  switch (nch) {
-#define FEF_NCH(N)                                                                                \
-  case N:                                                                                         \
-    hipLaunchKernelGGL((pair_split_kernel<F16, XB, N>), grid, dim3(128 * XB), 0, st, p.d_frag,    \
+#define FEF_CHAINS(A, B)                                                                      \
+  if (na == A && nb == B) {                                                                   \
+    hipLaunchKernelGGL((pair_split_pp_kernel<F16, A, B>), grid, dim3(512), 0, st, p.d_frag,   \
+                       t.d_xblocks, entries, items, (int32_t)t.nitems, head, t.d_grp_off, o,  \
+                       prec, pw, gap, partial);                                               \
+    return;                                                                                   \
+  }
+  FEF_CHAINS(1, 1) FEF_CHAINS(1, 2) FEF_CHAINS(2, 3) FEF_CHAINS(2, 4) FEF_CHAINS(3, 5)
+#undef FEF_CHAINS
+}
+
+template <bool F16, int XB>
+static void launch_split_chains(const fef_plan_s& p, int na, int nb, dim3 grid, hipStream_t st,
+                                const char* o, int prec, int pw, const double* gap,
+                                const Entry* entries, const WorkItem* items, double* partial,
+                                int32_t* head) {
+  const TileSet& t = p.tiles[prec];
+#define FEF_CHAINS(A, B)                                                                          \
+  if (na == A && nb == B) {                                                                       \
+    hipLaunchKernelGGL((pair_split_kernel<F16, XB, A, B>), grid, dim3(128 * XB), 0, st, p.d_frag, \
                        p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,                      \
                        (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);          \
-    break;
-    FEF_NCH(1) FEF_NCH(2) FEF_NCH(3) FEF_NCH(4) FEF_NCH(5) FEF_NCH(6) FEF_NCH(7) FEF_NCH(8)
-#undef FEF_NCH
+    return;                                                                                       \
   }
+  FEF_CHAINS(1, 1) FEF_CHAINS(1, 2) FEF_CHAINS(2, 3) FEF_CHAINS(2, 4) FEF_CHAINS(3, 5)
+#undef FEF_CHAINS
 }
 
 hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
                               fef_prec prec, const Entry* entries, const WorkItem* items,
                               double* partial, int32_t* head, int ncu, hipStream_t st) {
   const char* o = static_cast<const char*>(ops);
-  const int pw = p.geom[prec].pw, nch = p.geom[prec].kpad / 32;
+  const int pw = p.geom[prec].pw;
+  const int na = split_chain_a(pw), nb = split_chain_b(pw);
   const int xb = p.tiles[prec].xb;
-  if (pw > 80 || pw % 8 != 0 || nch < 1 || nch > 8) return hipErrorInvalidValue;
+  if (pw > 80 || pw < 8 || pw % 8 != 0) return hipErrorInvalidValue;
   if ((p.ops_header & 15) != 0) return hipErrorInvalidValue;  // 16-byte copies
-  // persistent grid: one workgroup per CU (XB = 4) or two (XB = 2)
-  const int64_t want = (int64_t)ncu * (xb == 2 ? 2 : 1);
-  const dim3 g((unsigned)std::min<int64_t>(want, std::max<int64_t>(p.tiles[prec].nitems, 1)));
+  // persistent grid, one workgroup per CU: xb = 2 runs the ping-pong kernel
+  // (eight waves), xb = 4 the four-unit kernel (eight waves)
+  const dim3 g((unsigned)std::min<int64_t>(ncu, std::max<int64_t>(p.tiles[prec].nitems, 1)));
   if (prec == FEF_FP16X2) {
-    if (xb == 4) launch_split_nch<true, 4>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_nch<true, 2>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    if (xb == 4) launch_split_chains<true, 4>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_pp<true>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else if (prec == FEF_BF16X2) {
-    if (xb == 4) launch_split_nch<false, 4>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_nch<false, 2>(p, nch, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    if (xb == 4) launch_split_chains<false, 4>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
+    else launch_split_pp<false>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
   } else {
     return hipErrorInvalidValue;
   }

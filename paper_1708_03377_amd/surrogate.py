@@ -84,3 +84,57 @@ class Ensemble:
                              device=self.device)
         F.fef_mlp_forward(self.nmember, n, X, self.stats, self.W, Y, self.stream())
         return Y[:self.nmember * n].view(self.nmember, n)
+
+
+# ---------------------------------------------------------------------------
+# Training recipe of the surrogate workload (8000 waters at 15 A): seeded
+# 1000-water boxes of the same density and cutoff (workload 1's style), 10
+# SCF steps each, the exact FP64 pair energies of every pair at R >= 6 A as
+# labels.  Seeds >= 100 never coincide with a named workload.
+TRAIN_SEEDS = (101, 102)
+HELDOUT_SEED = 103
+R_EXACT_ANGSTROM = 6.0
+
+
+def pair_dataset(ctx, r_min_bohr: float, niter: int = 10):
+    """Features X [n][17] and targets T [n] (device tensors) of the pairs of
+    ``ctx``'s system at R >= r_min_bohr, after niter SCF steps from the
+    generated orbitals, with the exact FP64 pair energies as targets; also
+    returns the pair indices."""
+    import torch
+    ctx.reset_orbitals()
+    ctx.scf(niter)
+    ctx.energies(F.PREC["f64"])
+    U = ctx.invariants()
+    far = np.nonzero(1.0 / ctx.system.pair_s >= r_min_bohr)[0].astype(np.int32)
+    idx = torch.from_numpy(far).to(ctx.device)
+    X, T = ctx.pair_features(U, idx, with_targets=True)
+    return X.clone(), T.clone(), far
+
+
+def training_set(seeds=TRAIN_SEEDS, n_water: int = 1000, cutoff: float = 15.0,
+                 niter: int = 10, device: str = "cuda:0"):
+    """The concatenated pair dataset of the seeded training boxes."""
+    import torch
+    import fefgen
+    from .runtime import Context
+    r_min = R_EXACT_ANGSTROM * fefgen.BOHR_PER_ANGSTROM
+    Xs, Ts = [], []
+    for sd in seeds:
+        ctx = Context(fefgen.surrogate_training_box(sd, n_water=n_water, cutoff=cutoff),
+                      device=device)
+        X, T, _ = pair_dataset(ctx, r_min, niter)
+        Xs.append(X)
+        Ts.append(T)
+        del ctx
+    return torch.cat(Xs), torch.cat(Ts)
+
+
+def train_ensemble(X, T, nmember: int = 5, seed: int = 0, epochs: int = 6, nb: int = 1024,
+                   lr: float = 2e-3, lr_final: float = 1e-4):
+    """A fresh ensemble with statistics fitted on (X, T), trained by the
+    library's kernels; returns (ensemble, loss per epoch)."""
+    ens = Ensemble(nmember=nmember, seed=seed, device=str(X.device))
+    ens.fit_stats(X, T)
+    hist = ens.train(X, T, epochs=epochs, nb=nb, lr=lr, lr_final=lr_final)
+    return ens, hist

@@ -17,9 +17,11 @@ def test_pair_flop_counts_config0():
     s = fefgen.make_system(0)
     # 28 water pairs, 2 ov_x ov_y P0 each
     assert bench.pair_flops(s) == 28 * 2 * 95 * 95 * 72
-    # issued: whole 96-row tiles; FP64 K = 72, split K = 3 * 72 rounded to 224
+    # issued: whole 96-row tiles; FP64 K = 72; split: the leading product
+    # over K = 72 rounded to 96 and the two cross products over 144 rounded
+    # to 160
     assert bench.pair_issued_flops(s, "f64") == 28 * 2 * 96 * 96 * 72
-    assert bench.pair_issued_flops(s, "fp16x2") == 28 * 2 * 96 * 96 * 224
+    assert bench.pair_issued_flops(s, "fp16x2") == 28 * 2 * 96 * 96 * (96 + 160)
     assert bench.pair_issued_flops(s, "bf16x2") / bench.pair_flops(s) > 3.0
 
 

@@ -280,12 +280,15 @@ def test_packed_scf_matches_oracle(torch, which, niter):
             np.testing.assert_allclose(D[oc[f]:oc[f + 1]], Dl[f].ravel(), rtol=0, atol=1e-10)
 
 
-@pytest.mark.parametrize("solute", [(64, 12, 24), (65, 13, 24)])
+@pytest.mark.parametrize("solute", [(49, 10, 8), (64, 12, 24), (65, 13, 24), (97, 20, 24),
+                                    (150, 29, 24)])
 def test_scf_large_fragment(torch, solute):
     """Fragments above 48 basis functions take the large-matrix eigensolver
-    (packed triangle in LDS); an odd size adds a decoupled padding index.
-    Orbital energies and densities against the oracle over two SCF steps, for
-    both the full and the packed coefficient paths."""
+    (Householder tridiagonalisation, multisection, inverse iteration,
+    back-transformation); the sizes cover both register layouts (up to 96
+    and up to 152 columns) with ragged padding.  Orbital energies and
+    densities against the oracle over two SCF steps, for both the full and
+    the packed coefficient paths, then the pair energies."""
     sysm = fefgen.make_two_class_system(31, solute, [(24, 5), (9, 2), (24, 5), (13, 6)], naux0=8)
     for packed in (False, True):
         ctx = ctx_for(sysm)
@@ -302,3 +305,23 @@ def test_scf_large_fragment(torch, solute):
         ref, _ = ofef.pair_energies(sysm, C, e)
         E2, _ = ctx.energies(PREC["f64"])
         assert np.max(np.abs(E2.cpu().numpy() - ref)) <= TOL_PAIR_F64
+
+
+@pytest.mark.parametrize("naux", [40, 76])
+@pytest.mark.parametrize("prec,tol", [("f64", TOL_PAIR_F64), ("f32", 1e-5)])
+def test_pair_energies_uncommon_rank(torch, naux, prec, tol):
+    """Factor ranks other than 8 and 72 take the plain kernels' generic
+    contraction length (20 k steps of 4): the rows past the padded rank are
+    read as zeros, so the energies match the oracle."""
+    sizes = [(24, 5), (13, 4), (24, 5), (9, 2), (30, 7), (24, 5), (7, 3)]
+    sysm = fefgen.make_random_system(41 + naux, sizes, naux=naux)
+    _say("pair energies", prec, "P0 =", naux, sysm.npair)
+    ref, ref_tot = ofef.pair_energies(sysm)
+    ctx = ctx_for(sysm)
+    for _ in range(2):  # a second call finds the first call's data in LDS
+        E2, tot = ctx.energies(PREC[prec])
+        torch.cuda.synchronize()
+        E2 = E2.cpu().numpy()
+        assert np.all(np.isfinite(E2))
+        assert np.max(np.abs(E2 - ref)) <= tol
+        assert int(ctx.flags.cpu()[0]) == 0
