@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X dense peaks for the arithmetic each pair mode's MFMA runs in
 PEAK = {"f64": ("mfma", 78.6e12), "f32": ("mfma", 157.3e12),
-        "bf16x2": ("mfma", 2.5e15), "fp16x2": ("mfma", 2.5e15)}
+        "bf16x2": ("mfma", 2.5e15), "fp16x2": ("mfma", 2.5e15), "bf16x3": ("mfma", 2.5e15)}
 HBM_PEAK = 8.0e12
 TOTAL_ERR_BAR = 1e-6  # Eh
 METRIC = ("fragment-pair E2 evals/s at 1 GPU, mixed/surrogate vs FP64 at "
@@ -57,7 +57,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=3, help="synthetic box id (0..4)")
-    ap.add_argument("--modes", default="f64,f32,bf16x2,fp16x2")
+    ap.add_argument("--modes", default=None,
+                    help="pair modes to time (default: the workload's own set)")
+    ap.add_argument("--surrogate-epochs", type=int, default=6)
+    ap.add_argument("--surrogate-threshold", type=float, default=1e-8,
+                    help="ensemble spread (Eh) above which a pair falls back to the exact kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -74,9 +78,9 @@ def pair_flops(sysm) -> float:
 
 def pair_issued_flops(sysm, mode: str) -> float:
     """Flops the MFMA units issue for one launch: whole 96-row tiles on both
-    sides and the padded contraction length (split modes: the leading
-    product over round_up(pw, 32) and the two cross products over
-    round_up(2 pw, 32), pw = round_up(P0, 8))."""
+    sides and the padded contraction length (split modes: the products of
+    order L over round_up((L + 1) pw, 32) contraction indices for L below the
+    number of terms, pw = round_up(P0, 8))."""
     ov = sysm.nocc.astype(np.int64) * (sysm.nbf - sysm.nocc).astype(np.int64)
     ld = ((ov + 95) // 96) * 96
     p0 = int(sysm.naux_class[0])
@@ -84,7 +88,8 @@ def pair_issued_flops(sysm, mode: str) -> float:
         k = ((p0 + 3) // 4) * 4
     else:
         pw = ((p0 + 7) // 8) * 8
-        k = ((pw + 31) // 32) * 32 + ((2 * pw + 31) // 32) * 32
+        nterm = 3 if mode == "bf16x3" else 2
+        k = sum((((lv + 1) * pw + 31) // 32) * 32 for lv in range(nterm))
     return float(np.sum(2.0 * ld[sysm.pair_x] * ld[sysm.pair_y] * k))
 
 
@@ -181,6 +186,88 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
                       f"all {sysm.npair} pairs"}
 
 
+# pair modes timed per workload when --modes is not given
+DEFAULT_MODES = {2: "f64,f32", 3: "f64,f32,bf16x2,fp16x2,bf16x3", 4: "f64,bf16x2,fp16x2,bf16x3"}
+
+
+def bench_surrogate(args, sysm, ctx, lib, torch, st, niter):
+    """The learned-surrogate pass of the 8000-water workload.  Untimed set-up:
+    the ensemble is trained by the library's kernels on the exact FP64 pair
+    energies of seeded 1000-water boxes at the same cutoff and density, and
+    checked on a held-out box.  Timed step (eager, event-timed): orbital
+    reset, niter SCF steps, fragment invariants, ensemble selection, half
+    transform and the exact BF16x2 kernel on every pair the ensemble
+    declines (all pairs below 6 A, every pair whose members disagree by more
+    than the threshold)."""
+    import fefgen
+    from paper_1708_03377_amd import surrogate as sg
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    r6 = sg.R_EXACT_ANGSTROM * fefgen.BOHR_PER_ANGSTROM
+    t0 = time.perf_counter()
+    X, T = sg.training_set(sg.TRAIN_SEEDS)
+    ens, hist = sg.train_ensemble(X, T, epochs=args.surrogate_epochs)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    ntrain = int(X.shape[0])
+    del X, T
+    # held-out box: error of the ensemble mean and spread of the members, in Eh
+    hctx = lib.Context(fefgen.surrogate_training_box(sg.HELDOUT_SEED))
+    Xh, Th, _ = sg.pair_dataset(hctx, r6, niter)
+    Y = ens.forward(Xh).cpu().numpy().astype(np.float64)
+    stt = ens.stats.cpu().numpy().astype(np.float64)
+    R2 = Xh[:, 0].cpu().numpy().astype(np.float64) ** 2
+    pred = (Y * stt[35] + stt[34]) / R2
+    truth = Th.cpu().numpy().astype(np.float64) / R2
+    spread = pred.max(0) - pred.min(0)
+    held = {"pairs": int(len(truth)), "rmse_Eh": float(np.sqrt(np.mean((pred.mean(0) - truth) ** 2))),
+            "median_spread_Eh": float(np.median(spread)),
+            "frac_spread_below_threshold": float(np.mean(spread <= args.surrogate_threshold))}
+    del hctx, Xh, Th
+    prec = lib.PREC["bf16x2"]
+    thr = args.surrogate_threshold
+
+    def step():
+        ctx.reset_orbitals()
+        ctx.scf(niter)
+        U = ctx.invariants()
+        return ctx.surrogate_energies(ens, U, r6, thr, prec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ge = [(ev(), ev()) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in ge:
+        a.record(st)
+        step()
+        b.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sel = ctx._select[:ctx.npair].cpu().numpy()
+    # the masked exact kernel alone, on the same selection
+    pe = [(ev(), ev()) for _ in range(args.steps)]
+    for a, b in pe:
+        a.record(st)
+        ctx.pair_energies_masked(prec, ctx._select)
+        b.record(st)
+    torch.cuda.synchronize()
+    return {"ms_per_step": 1e3 * wall / args.steps,
+            "gpu_ms_per_step": float(np.mean([a.elapsed_time(b) for a, b in ge])),
+            "stage_ms": [float("nan")] * 3,
+            "pair_ms": float(np.mean([a.elapsed_time(b) for a, b in pe])),
+            "tiles": lib.fef_plan_get_tiles(ctx.plan, prec), "unit_ms": [float("nan")],
+            "E_total": float(ctx.E2_total.cpu()[0]), "flags": int(ctx.flags.cpu()[0]),
+            "E2": ctx.E2_pair[:ctx.npair].cpu().numpy().copy(),
+            "surrogate": {"threshold_Eh": thr, "exact_below_A": sg.R_EXACT_ANGSTROM,
+                          "predicted_fraction": float(np.mean(sel == 0)),
+                          "exact_fraction": float(np.mean(sel != 0)),
+                          "training_pairs": ntrain, "training_boxes": list(sg.TRAIN_SEEDS),
+                          "epochs": args.surrogate_epochs, "train_s": round(train_s, 2),
+                          "final_loss": hist[-1] if hist else None,
+                          "heldout_box": sg.HELDOUT_SEED, "heldout": held,
+                          "exact_kernel": "bf16x2"}}
+
+
 def copy_probe(mib: int):
     """A plain device-to-device copy of known size (counter calibration)."""
     import torch
@@ -212,7 +299,7 @@ def main():
     spec = sysm.spec
     niter = spec.niter
     ctx = lib.Context(sysm, device="cuda:0")
-    modes = [m for m in args.modes.split(",") if m]
+    modes = [m for m in (args.modes or DEFAULT_MODES.get(args.workload, "f64")).split(",") if m]
     if "f64" not in modes:
         modes = ["f64"] + modes
     st = ctx.stream()
@@ -278,6 +365,11 @@ def main():
         print(f"[bench] mode {name}: {results[name]['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
 
+    if spec.cfg_id == 4:
+        print("[bench] surrogate: training, held-out check, timed passes", file=sys.stderr,
+              flush=True)
+        results["surrogate"] = bench_surrogate(args, sysm, ctx, lib, torch, st, niter)
+
     ref = results["f64"]
     ref_oracle = oracle_total(spec.name)
     modes_out = {}
@@ -285,22 +377,27 @@ def main():
         err_tot = abs(r["E_total"] - ref["E_total"])
         err_orc = abs(r["E_total"] - ref_oracle) if ref_oracle is not None else None
         err_pair = float(np.max(np.abs(r["E2"] - ref["E2"]))) if sysm.npair else 0.0
+        sur = "surrogate" in r
         modes_out[name] = {
             "pairs_per_s": sysm.npair / (r["ms_per_step"] / 1e3),
             "ms_per_step": round(r["ms_per_step"], 4),
             "gpu_ms_per_step": round(r["gpu_ms_per_step"], 4),
-            "scf_ms": round(r["stage_ms"][0], 4), "half_ms": round(r["stage_ms"][1], 4),
+            "scf_ms": None if sur else round(r["stage_ms"][0], 4),
+            "half_ms": None if sur else round(r["stage_ms"][1], 4),
             "pair_ms": round(r["pair_ms"], 4),
-            "pair_tflops": pair_flops(sysm) / (r["pair_ms"] / 1e3) / 1e12,
-            "half_plus_pair": {"median_ms": round(float(np.median(r["unit_ms"])), 4),
-                               "min_ms": round(float(np.min(r["unit_ms"])), 4),
-                               "max_ms": round(float(np.max(r["unit_ms"])), 4),
-                               "reps": len(r["unit_ms"]), "warmup": 5,
-                               "pairs_per_s": sysm.npair / (float(np.median(r["unit_ms"])) / 1e3)},
+            "pair_tflops": None if sur else pair_flops(sysm) / (r["pair_ms"] / 1e3) / 1e12,
+            "half_plus_pair": None if sur else {
+                "median_ms": round(float(np.median(r["unit_ms"])), 4),
+                "min_ms": round(float(np.min(r["unit_ms"])), 4),
+                "max_ms": round(float(np.max(r["unit_ms"])), 4),
+                "reps": len(r["unit_ms"]), "warmup": 5,
+                "pairs_per_s": sysm.npair / (float(np.median(r["unit_ms"])) / 1e3)},
             "tiles_xb_yc": list(r["tiles"]),
             "total_err_vs_f64": err_tot, "max_pair_err_vs_f64": err_pair,
             "total_err_vs_oracle": err_orc,
             "E2_total": r["E_total"], "flags": r["flags"]}
+        if sur:
+            modes_out[name]["surrogate"] = r["surrogate"]
     # the gate: total within 1 uEh of the oracle's own total when it is
     # stored for this workload, else of the GPU FP64 path's
     gate = "total_err_vs_oracle" if ref_oracle is not None else "total_err_vs_f64"
@@ -308,28 +405,39 @@ def main():
           and modes_out[m]["flags"] == 0]
     head = max(ok, key=lambda m: modes_out[m]["pairs_per_s"]) if ok else "f64"
     h = modes_out[head]
+    # the dominant kernel: the exact pair kernel of the headline mode (the
+    # surrogate pass runs the BF16x2 kernel on the pairs it declines)
+    kmode = "bf16x2" if head == "surrogate" else head
+    hk = modes_out[kmode]
     flops = pair_flops(sysm)
-    bound, peak = PEAK[head]
-    achieved = flops / (h["pair_ms"] / 1e3)
+    bound, peak = PEAK[kmode]
+    achieved = flops / (hk["pair_ms"] / 1e3)
+    classes = []
+    for c in range(sysm.nclass):
+        f = int(np.nonzero(sysm.cls == c)[0][0])
+        classes.append({"count": int(np.sum(sysm.cls == c)), "nbf": int(sysm.nbf[f]),
+                        "nocc": int(sysm.nocc[f]), "P": int(sysm.naux_class[c])})
     line = {
         "metric": METRIC, "value": h["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": h["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": head,
         "data": "synthetic (seeded liquid-like water box, random-init fragment data)",
         "config": {"workload": spec.name, "nfrag": int(sysm.nfrag), "npair": int(sysm.npair),
-                   "nbf": 24, "nocc": 5, "P": int(sysm.naux_class[0]),
-                   "cutoff_A": spec.cutoff, "niter": niter,
-                   "step": "HIP-graph replay: orbital reset + niter SCF steps + half "
-                           "transform + pair energies + total"},
-        "roofline": {"kernel": f"pair contraction ({head})", "bound": bound,
+                   "fragment_classes": classes, "cutoff_A": spec.cutoff, "niter": niter,
+                   "step": ("eager: orbital reset + niter SCF steps + fragment invariants + "
+                            "ensemble selection + half transform + exact pair energies of the "
+                            "declined pairs + total" if head == "surrogate" else
+                            "HIP-graph replay: orbital reset + niter SCF steps + half "
+                            "transform + pair energies + total")},
+        "roofline": {"kernel": f"pair contraction ({kmode})", "bound": bound,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": traffic_from_profiles(head, spec.name),
+                     "traffic": traffic_from_profiles(kmode, spec.name),
                      "algorithmic_flops_per_launch": flops,
-                     "issued_flops_per_launch": pair_issued_flops(sysm, head),
-                     "issued_frac": pair_issued_flops(sysm, head) / (h["pair_ms"] / 1e3) / peak,
-                     "launch_ms": h["pair_ms"],
-                     "operand_bytes": pair_operand_bytes(ctx, lib.PREC[head])},
+                     "issued_flops_per_launch": pair_issued_flops(sysm, kmode),
+                     "issued_frac": pair_issued_flops(sysm, kmode) / (hk["pair_ms"] / 1e3) / peak,
+                     "launch_ms": hk["pair_ms"],
+                     "operand_bytes": pair_operand_bytes(ctx, lib.PREC[kmode])},
         "accuracy_gate": {"bar_Eh": TOTAL_ERR_BAR, "against": "oracle" if ref_oracle is not None
                           else "gpu_f64", "oracle_total": ref_oracle},
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],

@@ -77,7 +77,10 @@ typedef enum {
   FEF_F32 = 1,     /* FP32 operands, FP32 MFMA                              */
   FEF_BF16X2 = 2,  /* x = hi + lo in BF16; hi*hi' + hi*lo' + lo*hi', FP32 acc */
   FEF_FP16X2 = 3,  /* same with FP16 and a per-fragment power-of-two scale  */
-  FEF_NPREC = 4
+  FEF_BF16X3 = 4,  /* x = hi + mid + lo in BF16; the six products of order up
+                      to two (hi*hi'; hi*mid' + mid*hi'; hi*lo' + mid*mid' +
+                      lo*hi'), FP32 acc                                      */
+  FEF_NPREC = 5
 } fef_prec;
 
 /* Fragment system, HOST memory, read once by fef_plan_create. */

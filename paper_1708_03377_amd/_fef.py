@@ -25,7 +25,7 @@ FEF_E_UNSUPPORTED = -6
 FEF_FLAG_GAP = 1
 FEF_FLAG_NONFINITE = 2
 
-PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
+PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3, "bf16x3": 4}
 
 Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)

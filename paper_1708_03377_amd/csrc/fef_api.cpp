@@ -37,11 +37,13 @@ void free_plan(fef_plan_s* p) {
 
 OpsGeom geom_of(int prec, int P0) {
   switch (prec) {
-    case FEF_F64: return {8, (int)round_up(P0, 4), 0};
-    case FEF_F32: return {4, (int)round_up(P0, 4), 0};
+    case FEF_F64: return {8, (int)round_up(P0, 4), 0, 1};
+    case FEF_F32: return {4, (int)round_up(P0, 4), 0, 1};
     default: {
-      const int pw = (int)round_up(P0, 8);
-      return {2, 32 * (split_chain_a(pw) + split_chain_b(pw)), pw};
+      const int pw = (int)round_up(P0, 8), nt = split_nterm(prec);
+      int kp = 0;
+      for (int l = 0; l < nt; ++l) kp += 32 * split_chain(l, pw);
+      return {2, kp, pw, nt};
     }
   }
 }
@@ -49,12 +51,12 @@ OpsGeom geom_of(int prec, int P0) {
 // operand block bytes of one fragment (one role)
 int64_t operand_bytes(const OpsGeom& g, int prec, int64_t ld) {
   if (prec == FEF_F64 || prec == FEF_F32) return round_up((int64_t)g.kpad * ld * g.elem_bytes, 256);
-  return round_up(ld * (2 * g.pw + 8) * g.elem_bytes, 256);
+  return round_up(ld * (g.nterm * g.pw + 8) * g.elem_bytes, 256);
 }
 
 // default pair-kernel tiling per mode: (x units per block, entries per item)
 void default_tiles(int prec, int& xb, int& yc) {
-  xb = (prec == FEF_F64 || prec == FEF_F32) ? 1 : 4;
+  xb = (prec == FEF_F64 || prec == FEF_F32) ? 1 : prec == FEF_BF16X3 ? 2 : 4;
   yc = 16;
 }
 

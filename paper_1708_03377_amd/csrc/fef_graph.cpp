@@ -133,8 +133,11 @@ fef_status fef_autotune(fef_plan p, const void* ops, const double* eps, fef_prec
     for (int xb : {1, 2})
       for (int yc : ycs) cand.push_back({xb, yc});
   } else {
+    // three-term operands keep 84 registers of x resident: only the
+    // ping-pong kernel (xb = 2) holds them without spilling
     for (int xb : {2, 4})
-      for (int yc : ycs) cand.push_back({xb, yc});
+      if (xb == 2 || prec != FEF_BF16X3)
+        for (int yc : ycs) cand.push_back({xb, yc});
   }
   // the candidates write their results into library-owned scratch, so the
   // caller's E2_pair / E2_total keep their contents

@@ -75,11 +75,14 @@ struct HtTask {
 //   12 banks apart); the leading product runs over round_up(pw, 32) and the
 //   two cross products over round_up(2 pw, 32) contraction indices, kpad
 //   is their sum.
-// Split modes: MFMA chunks (32 contraction indices each) of the leading
-// product hi.hi (chain A) and of the two cross products (chain B) for a
-// plane width pw.
-__host__ __device__ constexpr int split_chain_a(int pw) { return (pw + 31) / 32; }
-__host__ __device__ constexpr int split_chain_b(int pw) { return (2 * pw + 31) / 32; }
+// Split modes: a value is stored as nterm 16-bit terms (planes 0 = hi,
+// 1 = mid or lo, 2 = lo).  The products of order L (the sum of the two
+// terms' plane indices) form chain L; it runs over (L + 1) pw contraction
+// indices, ceil((L + 1) pw / 32) MFMA chunks of 32.
+__host__ __device__ constexpr int split_chain(int level, int pw) {
+  return ((level + 1) * pw + 31) / 32;
+}
+__host__ __device__ constexpr int split_nterm(int prec) { return prec == FEF_BF16X3 ? 3 : 2; }
 
 // Eigensolver workspace (doubles) per fragment with nbf > 48, for the
 // largest such nbf: the Jacobi path keeps V^T and a product matrix
@@ -99,6 +102,7 @@ struct OpsGeom {
   int elem_bytes;   // bytes per stored element
   int kpad;         // padded contraction length
   int pw;           // plane width (split modes)
+  int nterm;        // stored terms per value (split modes)
 };
 
 // Work items come in kQueues groups of contiguous x-blocks (locality order,
@@ -141,7 +145,7 @@ struct fef_plan_s {
   std::vector<int64_t> off_G;
   std::vector<int32_t> naux_cls_off;  // prefix sums of P_c over classes
   int64_t nB = 0, nC = 0, nEps = 0, nBov = 0, nW = 0, nG = 0, nGap = 0;
-  int64_t ops_bytes[FEF_NPREC] = {0, 0, 0, 0};
+  int64_t ops_bytes[FEF_NPREC] = {};
   fef::OpsGeom geom[FEF_NPREC];
   // eigen-solver groups: fragments by size class
   std::vector<int32_t> eig_small, eig_mid, eig_large;
@@ -162,7 +166,7 @@ struct fef_plan_s {
   fef::TileSet tiles[FEF_NPREC];
   // captured passes alive per mode: while any holds a mode's tile tables,
   // a retune keeps the superseded tables (freed with the plan)
-  int32_t graphs_live[FEF_NPREC] = {0, 0, 0, 0};
+  int32_t graphs_live[FEF_NPREC] = {};
   std::vector<fef::TileSet> retired_tiles;
   fef::HtTask* d_ht = nullptr;
   int64_t* d_off_G = nullptr;

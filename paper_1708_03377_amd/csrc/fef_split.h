@@ -1,6 +1,7 @@
-// Two-term operand splitting shared by the split-precision packers.
+// Multi-term operand splitting shared by the split-precision packers.
 #pragma once
 
+#include "fef_internal.h"
 #include "fef_device.h"
 
 namespace fef {
@@ -32,6 +33,23 @@ __device__ inline void split2(double x, uint16_t& hi, uint16_t& lo) {
   } else {
     hi = bf16_rne((float)x);
     lo = bf16_rne((float)(x - (double)__uint_as_float(((uint32_t)hi) << 16)));
+  }
+}
+
+// x = t0 + t1 + ... in the 16-bit format of mode PREC: FP16X2 and BF16X2 as
+// split2, BF16X3 as three BF16 terms t_k = rn(x - t_0 - ... - t_{k-1}) with
+// the residuals taken in FP64.
+template <int PREC, int NTERM>
+__device__ inline void split_terms(double x, uint16_t (&t)[NTERM]) {
+  if constexpr (NTERM == 2) {
+    split2<PREC == FEF_FP16X2>(x, t[0], t[1]);
+  } else {
+    double r = x;
+#pragma unroll
+    for (int k = 0; k < NTERM; ++k) {
+      t[k] = bf16_rne((float)r);
+      r -= (double)__uint_as_float(((uint32_t)t[k]) << 16);
+    }
   }
 }
 

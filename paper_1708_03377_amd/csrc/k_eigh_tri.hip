@@ -309,79 +309,96 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_values_kernel(
     if (j == 0 || lam[j] - lam[j - 1] > ortol) {
       int j1 = j;
       while (j1 + 1 < n && lam[j1 + 1] - lam[j1] <= ortol) ++j1;
-      double* A_ = W.fac + (size_t)j * 6 * n;  // diagonal after elimination
-      double* B_ = A_ + n;                     // first superdiagonal
-      double* D_ = B_ + n;                     // second superdiagonal (pivoting fill)
-      double* L_ = D_ + n;                     // multipliers
-      double* P_ = L_ + n;                     // 1.0 where rows k, k+1 were swapped
-      double* x = P_ + n;                      // iterate
+      // this thread's six work vectors, interleaved with the other threads'
+      // (entry i of vector v at (v n + i) n + j), so that threads stepping
+      // through their recurrences together touch neighbouring addresses
+      double* base = W.fac + j;
+      const size_t sv = (size_t)n * n;
+      auto A_ = [&](int i) -> double& { return base[(size_t)i * n]; };           // diagonal of U
+      auto B_ = [&](int i) -> double& { return base[sv + (size_t)i * n]; };      // first superdiagonal
+      auto D_ = [&](int i) -> double& { return base[2 * sv + (size_t)i * n]; };  // second superdiagonal
+      auto L_ = [&](int i) -> double& { return base[3 * sv + (size_t)i * n]; };  // multipliers
+      auto P_ = [&](int i) -> double& { return base[4 * sv + (size_t)i * n]; };  // 1: rows i, i+1 swapped
+      auto x = [&](int i) -> double& { return base[5 * sv + (size_t)i * n]; };   // iterate
       double prev = 0.0;
       for (int jj = j; jj <= j1; ++jj) {
         double lm = lam[jj];
         if (jj > j && lm - prev < 10.0 * DBL_EPSILON * fabs(lm))
           lm = prev + 10.0 * DBL_EPSILON * fabs(lm);
         prev = lm;
-        // T - lm I = P L U with row interchanges between neighbours
-        for (int i = 0; i < n; ++i) {
-          A_[i] = dg[i] - lm;
-          B_[i] = ee[i];
-        }
+        // T - lm I = P L U with row interchanges between neighbours; the
+        // current row's diagonal and superdiagonal ride in registers
+        double ak = dg[0] - lm, bk = n > 1 ? ee[0] : 0.0;
         for (int k = 0; k + 1 < n; ++k) {
           const double ck = ee[k];
-          if (fabs(A_[k]) >= fabs(ck)) {
-            if (A_[k] == 0.0) A_[k] = tiny;
-            const double l = ck / A_[k];
-            L_[k] = l;
-            P_[k] = 0.0;
-            D_[k] = 0.0;
-            A_[k + 1] -= l * B_[k];
+          double ak1 = dg[k + 1] - lm, bk1 = k + 2 < n ? ee[k + 1] : 0.0;
+          if (fabs(ak) >= fabs(ck)) {
+            if (ak == 0.0) ak = tiny;
+            const double l = ck / ak;
+            L_(k) = l;
+            P_(k) = 0.0;
+            D_(k) = 0.0;
+            A_(k) = ak;
+            B_(k) = bk;
+            ak1 -= l * bk;
           } else {
-            const double l = A_[k] / ck;
-            L_[k] = l;
-            P_[k] = 1.0;
-            const double bk = B_[k], ak1 = A_[k + 1], bk1 = B_[k + 1];
-            A_[k] = ck;
-            B_[k] = ak1;
-            D_[k] = bk1;
-            A_[k + 1] = bk - l * ak1;
-            B_[k + 1] = -l * bk1;
+            const double l = ak / ck;
+            L_(k) = l;
+            P_(k) = 1.0;
+            A_(k) = ck;
+            B_(k) = ak1;
+            D_(k) = bk1;
+            const double na = bk - l * ak1;
+            bk1 = -l * bk1;
+            ak1 = na;
           }
+          ak = ak1;
+          bk = bk1;
         }
+        A_(n - 1) = ak;
+        B_(n - 1) = 0.0;
         for (int i = 0; i < n; ++i)
-          if (fabs(A_[i]) < tiny) A_[i] = A_[i] < 0.0 ? -tiny : tiny;
-        for (int i = 0; i < n; ++i) x[i] = start_entry(jj, i);
+          if (fabs(A_(i)) < tiny) A_(i) = A_(i) < 0.0 ? -tiny : tiny;
+        for (int i = 0; i < n; ++i) x(i) = start_entry(jj, i);
         for (int itn = 0; itn < 3; ++itn) {
           double mx = 0.0;
-          for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[i]));
+          for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x(i)));
           const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-          for (int i = 0; i < n; ++i) x[i] *= inv;
+          for (int i = 0; i < n; ++i) x(i) *= inv;
+          // forward: the row interchanges and multipliers; backward: U
+          double xk = x(0);
           for (int k = 0; k + 1 < n; ++k) {
-            if (P_[k] != 0.0) {
-              const double t = x[k];
-              x[k] = x[k + 1];
-              x[k + 1] = t;
+            double x1 = x(k + 1);
+            if (P_(k) != 0.0) {
+              const double t = xk;
+              xk = x1;
+              x1 = t;
             }
-            x[k + 1] -= L_[k] * x[k];
+            x1 -= L_(k) * xk;
+            x(k) = xk;
+            xk = x1;
           }
+          x(n - 1) = xk;
+          double x1 = 0.0, x2 = 0.0;  // x(k + 1), x(k + 2)
           for (int k = n - 1; k >= 0; --k) {
-            double s = x[k];
-            if (k + 1 < n) s -= B_[k] * x[k + 1];
-            if (k + 2 < n) s -= D_[k] * x[k + 2];
-            x[k] = s / A_[k];
+            const double xv = (x(k) - B_(k) * x1 - D_(k) * x2) / A_(k);
+            x(k) = xv;
+            x2 = x1;
+            x1 = xv;
           }
           for (int q = j; q < jj; ++q) {
             const double* zq = W.Z + (size_t)q * ld;
             double dot = 0.0;
-            for (int i = 0; i < n; ++i) dot = fma(zq[i], x[i], dot);
-            for (int i = 0; i < n; ++i) x[i] -= dot * zq[i];
+            for (int i = 0; i < n; ++i) dot = fma(zq[i], x(i), dot);
+            for (int i = 0; i < n; ++i) x(i) -= dot * zq[i];
           }
           double nrm = 0.0;
-          for (int i = 0; i < n; ++i) nrm = fma(x[i], x[i], nrm);
+          for (int i = 0; i < n; ++i) nrm = fma(x(i), x(i), nrm);
           const double r = 1.0 / sqrt(nrm);
-          for (int i = 0; i < n; ++i) x[i] *= r;
+          for (int i = 0; i < n; ++i) x(i) *= r;
         }
         double* zj = W.Z + (size_t)jj * ld;
-        for (int i = 0; i < n; ++i) zj[i] = x[i];
+        for (int i = 0; i < n; ++i) zj[i] = x(i);
         for (int i = n; i < ld; ++i) zj[i] = 0.0;
       }
     }

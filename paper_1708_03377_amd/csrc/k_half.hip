@@ -239,32 +239,34 @@ __global__ __launch_bounds__(kPackThreads) void ht_pack_small_kernel(
       hdr[2 * f] = 1.0 / sL;
       hdr[2 * f + 1] = 1.0 / sR;
     }
-    const int xs = 2 * pw + 8;
+    constexpr int NTERM = split_nterm(PREC);
+    const int xs = NTERM * pw + 8;
     uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
     uint16_t* R = right ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
-    // rows [ia][hi plane | lo plane | 8 zeros], written in 16-byte pieces: a
-    // thread splits eight consecutive q of one row and stores their hi and
-    // lo words; rows >= ov and q >= P0 are zeros, so no separate zero fill
+    // rows [ia][plane 0 | plane 1 | ... | 8 zeros], written in 16-byte
+    // pieces: a thread splits eight consecutive q of one row and stores their
+    // terms; rows >= ov and q >= P0 are zeros, so no separate zero fill
     const int nqc = pw / 8;
     const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
     if (R)
       for (int e = threadIdx.x; e < kTile * (nqc + 1); e += kPackThreads) {
         const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
         if (c == nqc) {
-          *reinterpret_cast<u16x8*>(R + ia * xs + 2 * pw) = z8;
+          *reinterpret_cast<u16x8*>(R + ia * xs + NTERM * pw) = z8;
           continue;
         }
-        u16x8 h, l;
+        u16x8 h[NTERM];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int q = 8 * c + u;
-          uint16_t hv = 0, lv = 0;
-          if (ia < ov && q < P0) split2<kF16>(Bs[q * kBld + ia] * sR, hv, lv);
-          h[u] = hv;
-          l[u] = lv;
+          uint16_t tv[NTERM] = {};
+          if (ia < ov && q < P0) split_terms<PREC, NTERM>(Bs[q * kBld + ia] * sR, tv);
+#pragma unroll
+          for (int k = 0; k < NTERM; ++k) h[k][u] = tv[k];
         }
-        *reinterpret_cast<u16x8*>(R + ia * xs + 8 * c) = h;
-        *reinterpret_cast<u16x8*>(R + ia * xs + pw + 8 * c) = l;
+#pragma unroll
+        for (int k = 0; k < NTERM; ++k)
+          *reinterpret_cast<u16x8*>(R + ia * xs + k * pw + 8 * c) = h[k];
       }
     __syncthreads();  // Bs is rewritten with W^T below
     const int wld = P0 + 1;
@@ -284,20 +286,21 @@ __global__ __launch_bounds__(kPackThreads) void ht_pack_small_kernel(
     for (int e = threadIdx.x; e < kTile * (nqc + 1); e += kPackThreads) {
       const int ia = e / (nqc + 1), c = e - (e / (nqc + 1)) * (nqc + 1);
       if (c == nqc) {
-        *reinterpret_cast<u16x8*>(L + ia * xs + 2 * pw) = z8;
+        *reinterpret_cast<u16x8*>(L + ia * xs + NTERM * pw) = z8;
         continue;
       }
-      u16x8 h, l;
+      u16x8 h[NTERM];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = 8 * c + u;
-        uint16_t hv = 0, lv = 0;
-        if (ia < ov && q < P0) split2<kF16>(Bs[ia * wld + q] * sL, hv, lv);
-        h[u] = hv;
-        l[u] = lv;
+        uint16_t tv[NTERM] = {};
+        if (ia < ov && q < P0) split_terms<PREC, NTERM>(Bs[ia * wld + q] * sL, tv);
+#pragma unroll
+        for (int k = 0; k < NTERM; ++k) h[k][u] = tv[k];
       }
-      *reinterpret_cast<u16x8*>(L + ia * xs + 8 * c) = h;
-      *reinterpret_cast<u16x8*>(L + ia * xs + pw + 8 * c) = l;
+#pragma unroll
+      for (int k = 0; k < NTERM; ++k)
+        *reinterpret_cast<u16x8*>(L + ia * xs + k * pw + 8 * c) = h[k];
     }
   }
 }
@@ -405,6 +408,7 @@ hipError_t launch_half_transform(const fef_plan_s& p, const double* B, const dou
       case FEF_F64: FEF_FUSED(FEF_F64); break;
       case FEF_F32: FEF_FUSED(FEF_F32); break;
       case FEF_BF16X2: FEF_FUSED(FEF_BF16X2); break;
+      case FEF_BF16X3: FEF_FUSED(FEF_BF16X3); break;
       default: FEF_FUSED(FEF_FP16X2); break;
     }
 #undef FEF_FUSED

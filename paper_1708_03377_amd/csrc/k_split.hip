@@ -1,25 +1,24 @@
-// Two-term split-precision pair contraction (BF16 or FP16 operands, FP32
-// MFMA accumulation, FP64 weighting and sums).
+// Split-precision pair contraction (BF16 or FP16 terms, FP32 MFMA
+// accumulation, FP64 weighting and sums).
 //
-// Each operand value x is split as x = hi + lo with hi = rn(x), lo = rn(x - hi)
-// (rn = round to nearest even in the 16-bit format).  The product keeps the
-// three leading terms
-//     x y ~ hi_x hi_y + (hi_x lo_y + lo_x hi_y)
-// and drops lo_x lo_y.  Each fragment stores one row per ia: [hi | lo], each
-// plane pw = round_up(P0, 8) wide, then 8 zeros.  The leading product and
-// the two cross products run as two MFMA chains with separate FP32
-// accumulators, added once per element in the epilogue:
-//     chain A (NA chunks of 32): x hi . y hi,
-//     chain B (NB chunks of 32): x [hi | lo] . y [lo | hi],
-// padded with the row's zero tail.  Within one MFMA instruction the
-// hardware drops the low bits of addends far below the largest one; a cross
-// product is about 2^-9 (BF16) or 2^-12 (FP16, relative to the scaled
-// operand) of a leading product, so sharing an accumulator with the leading
-// products would truncate the cross terms systematically.  pw is a multiple
-// of 8, so the 8 contraction indices a lane feeds one MFMA never straddle
-// two planes.  FP16 operands carry a per-fragment power-of-two scale that
-// places each operand's largest value in [2^13, 2^14), keeping lo parts out
-// of the subnormal range; the scales are undone exactly in FP64.
+// Each operand value x is stored as nterm 16-bit terms: two (BF16X2,
+// FP16X2: x ~ t0 + t1) or three (BF16X3: x ~ t0 + t1 + t2), each term the
+// nearest 16-bit value to what the earlier terms leave.  A stored row (one
+// per ia) holds the term planes t0 | t1 [| t2], each pw = round_up(P0, 8)
+// wide, then 8 zeros.  The product keeps the terms of order up to nterm - 1
+// (order = the sum of the two terms' plane indices): order 0 is t0 t0',
+// order 1 is t0 t1' + t1 t0', order 2 is t0 t2' + t1 t1' + t2 t0'.  The
+// products of one order form one MFMA chain: x reads the planes 0..L
+// concatenated, y the same planes in reverse order, over (L + 1) pw
+// contraction indices padded to chunks of 32 with the row's zero tail.  The
+// chains run from the highest order to the lowest into one FP32
+// accumulator, so that no MFMA instruction adds a small high-order product
+// next to a leading one: within one instruction the hardware drops the low
+// bits of addends far below the largest one.  pw is a multiple of 8, so the
+// 8 contraction indices a lane feeds one MFMA never straddle two planes.
+// FP16 operands carry a per-fragment power-of-two scale that places each
+// operand's largest value in [2^13, 2^14), keeping the low terms out of the
+// subnormal range; the scales are undone exactly in FP64.
 #include <algorithm>
 
 #include "fef_internal.h"
@@ -55,51 +54,55 @@ __global__ __launch_bounds__(256) void split_scale_kernel(const FragInfo* __rest
   }
 }
 
-// Writes both operands of a fragment, layout [ld][2 pw + 8]: row m holds
-// hi(k = 0..P0-1), zeros up to pw, then lo(k), zeros, then 8 zeros; rows
-// m >= ov are zero.
-template <bool kFp16>
+// Writes both operands of a fragment, layout [ld][nterm pw + 8]: row m holds
+// term plane 0 (k = 0..P0-1, zeros up to pw), plane 1, [plane 2,] then 8
+// zeros; rows m >= ov are zero.
+template <int PREC>
 __global__ __launch_bounds__(256) void split_pack_kernel(const FragInfo* __restrict__ frag,
                                                          const int32_t* __restrict__ list,
-                                                         int P0, int pw, int prec,
+                                                         int P0, int pw,
                                                          const double* __restrict__ bov,
                                                          const double* __restrict__ w,
                                                          const double* __restrict__ hdr,
                                                          char* __restrict__ ops) {
+  constexpr int NTERM = split_nterm(PREC);
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int tile = blockIdx.y;
   if (tile >= fi.ntile) return;
   const double sL = 1.0 / hdr[2 * f];
   const double sR = 1.0 / hdr[2 * f + 1];
-  uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[prec]);
-  uint16_t* R = fi.off_R[prec] >= 0 ? reinterpret_cast<uint16_t*>(ops + fi.off_R[prec]) : nullptr;
+  uint16_t* L = reinterpret_cast<uint16_t*>(ops + fi.off_L[PREC]);
+  uint16_t* R = fi.off_R[PREC] >= 0 ? reinterpret_cast<uint16_t*>(ops + fi.off_R[PREC]) : nullptr;
   const int nchunk = pw / 8;
-  const int row2 = 2 * pw + 8;
+  const int row = NTERM * pw + 8;
   const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int m = tile * kTile + threadIdx.x; m < (tile + 1) * kTile; m += blockDim.x) {
-    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + 2 * pw) = z;
-    if (R) *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + 2 * pw) = z;
+    *reinterpret_cast<u16x8*>(L + (int64_t)m * row + NTERM * pw) = z;
+    if (R) *reinterpret_cast<u16x8*>(R + (int64_t)m * row + NTERM * pw) = z;
   }
   for (int e = threadIdx.x; e < kTile * nchunk; e += blockDim.x) {
     const int m = tile * kTile + e / nchunk;
     const int k0 = (e % nchunk) * 8;
-    u16x8 lh, ll, rh, rl;
+    u16x8 lt[NTERM], rt[NTERM];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u;
-      uint16_t a = 0, b = 0, c = 0, d = 0;
+      uint16_t a[NTERM] = {}, c[NTERM] = {};
       if (m < fi.ov && k < P0) {
-        split2<kFp16>(w[fi.off_w + (int64_t)k * fi.ov + m] * sL, a, b);
-        if (R) split2<kFp16>(bov[fi.off_bov + (int64_t)k * fi.ov + m] * sR, c, d);
+        split_terms<PREC, NTERM>(w[fi.off_w + (int64_t)k * fi.ov + m] * sL, a);
+        if (R) split_terms<PREC, NTERM>(bov[fi.off_bov + (int64_t)k * fi.ov + m] * sR, c);
       }
-      lh[u] = a; ll[u] = b; rh[u] = c; rl[u] = d;
+#pragma unroll
+      for (int t = 0; t < NTERM; ++t) {
+        lt[t][u] = a[t];
+        rt[t][u] = c[t];
+      }
     }
-    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + k0) = lh;
-    *reinterpret_cast<u16x8*>(L + (int64_t)m * row2 + pw + k0) = ll;
-    if (R) {
-      *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + k0) = rh;
-      *reinterpret_cast<u16x8*>(R + (int64_t)m * row2 + pw + k0) = rl;
+#pragma unroll
+    for (int t = 0; t < NTERM; ++t) {
+      *reinterpret_cast<u16x8*>(L + (int64_t)m * row + t * pw + k0) = lt[t];
+      if (R) *reinterpret_cast<u16x8*>(R + (int64_t)m * row + t * pw + k0) = rt[t];
     }
   }
 }
@@ -116,13 +119,17 @@ hipError_t launch_pack_split(const fef_plan_s& p, const double* bov, const doubl
   if (prec == FEF_FP16X2) {
     hipLaunchKernelGGL(split_scale_kernel<true>, dim3(ng), dim3(256), 0, st, p.d_frag,
                        p.d_ht_generic, p.P0, bov, w, hdr);
-    hipLaunchKernelGGL(split_pack_kernel<true>, dim3(ng, maxtile), dim3(256), 0, st, p.d_frag,
-                       p.d_ht_generic, p.P0, pw, (int)prec, bov, w, hdr, o);
-  } else if (prec == FEF_BF16X2) {
+    hipLaunchKernelGGL(split_pack_kernel<FEF_FP16X2>, dim3(ng, maxtile), dim3(256), 0, st,
+                       p.d_frag, p.d_ht_generic, p.P0, pw, bov, w, hdr, o);
+  } else if (prec == FEF_BF16X2 || prec == FEF_BF16X3) {
     hipLaunchKernelGGL(split_scale_kernel<false>, dim3(ng), dim3(256), 0, st, p.d_frag,
                        p.d_ht_generic, p.P0, bov, w, hdr);
-    hipLaunchKernelGGL(split_pack_kernel<false>, dim3(ng, maxtile), dim3(256), 0, st, p.d_frag,
-                       p.d_ht_generic, p.P0, pw, (int)prec, bov, w, hdr, o);
+    if (prec == FEF_BF16X2)
+      hipLaunchKernelGGL(split_pack_kernel<FEF_BF16X2>, dim3(ng, maxtile), dim3(256), 0, st,
+                         p.d_frag, p.d_ht_generic, p.P0, pw, bov, w, hdr, o);
+    else
+      hipLaunchKernelGGL(split_pack_kernel<FEF_BF16X3>, dim3(ng, maxtile), dim3(256), 0, st,
+                         p.d_frag, p.d_ht_generic, p.P0, pw, bov, w, hdr, o);
   } else {
     return hipErrorInvalidValue;
   }
@@ -153,6 +160,65 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// The chains of one split contraction for a lane with k-group lk: x chunk m
+// reads the stored row at kk = 32 m + 8 lk (the planes concatenated); the
+// chain of order L pairs it with y plane L - i, i = kk / pw, at the same
+// offset within the plane, while kk < (L + 1) pw, and with the row's zero
+// tail beyond.  N0, N1, N2: the chunks of orders 0, 1, 2 (N2 = 0 for two
+// terms); NX = the chunks of the highest order, which cover every x chunk.
+template <bool kFp16, int NTERM, int N0, int N1, int N2>
+struct SplitChains {
+  static constexpr int NX = NTERM == 3 ? N2 : N1;
+  int xoff[NX], y0[N0], y1[N1], y2[N2 > 0 ? N2 : 1];
+  __device__ __forceinline__ SplitChains(int pw, int lk) {
+    const int tail = NTERM * pw;
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      const int kk = 32 * m + 8 * lk;
+      xoff[m] = kk < tail ? kk : tail;
+      const int i = kk / pw, in = kk - (kk / pw) * pw;
+      if (m < N0) y0[m] = kk < pw ? kk : tail;
+      if (m < N1) y1[m] = kk < 2 * pw ? (1 - i) * pw + in : tail;
+      if (N2 > 0 && m < N2) y2[m] = kk < 3 * pw ? (2 - i) * pw + in : tail;
+    }
+  }
+  // x rows r (at L + 16 i xs) of TI tiles, every chunk
+  template <int TI>
+  __device__ __forceinline__ void load_x(u16x8 (&xa)[TI][NX], const uint16_t* L, int xs) const {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+  }
+  template <int TI, int TJ, int NC>
+  __device__ __forceinline__ static void chain(f4 (&acc)[TI][TJ], const u16x8 (&xa)[TI][NX],
+                                               const uint16_t* Yb, int xs, const int (&yo)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u16x8 b[TJ];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yo[c]);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+    }
+  }
+  // acc += the whole contraction against the y rows at Yb + 16 j xs, highest
+  // order first
+  template <int TI, int TJ>
+  __device__ __forceinline__ void contract(f4 (&acc)[TI][TJ], const u16x8 (&xa)[TI][NX],
+                                           const uint16_t* Yb, int xs) const {
+    if constexpr (N2 > 0) chain<TI, TJ, N2>(acc, xa, Yb, xs, y2);
+    chain<TI, TJ, N1>(acc, xa, Yb, xs, y1);
+    chain<TI, TJ, N0>(acc, xa, Yb, xs, y0);
+  }
+};
+
+// row stride bound (16-bit words) of a stored row, pw <= 80
+template <int NTERM>
+constexpr int split_row_max() { return NTERM * 80 + 8; }
+
 // Persistent split-precision pair kernel.  Work items as in the plain
 // kernel.  A workgroup serves XB x units with two waves each (128 XB
 // threads; XB = 2 runs two workgroups per CU, whose barriers are
@@ -166,9 +232,7 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
 // knows that reads of the current one never wait for the copy into the next.
 // MFMA operand lane layout (16x16x32): row (or column) = lane % 16,
 // contraction indices 8 (lane / 16) .. +7.
-constexpr int kXsMax = 2 * 80 + 8;  // row stride bound (pw <= 80)
-
-template <bool kFp16, int XB, int NA, int NB>
+template <bool kFp16, int XB, int NTERM, int N0, int N1, int N2>
 __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
@@ -177,8 +241,10 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
   constexpr int NT = 128 * XB, NW = 2 * XB;
   constexpr int TI = 3, TJ = 6, TJP = 3;
-  __shared__ __align__(16) uint16_t YsA[kTile * kXsMax];
-  __shared__ __align__(16) uint16_t YsB[kTile * kXsMax];
+  typedef SplitChains<kFp16, NTERM, N0, N1, N2> Ch;
+  constexpr int NX = Ch::NX;
+  __shared__ __align__(16) uint16_t YsA[kTile * split_row_max<NTERM>()];
+  __shared__ __align__(16) uint16_t YsB[kTile * split_row_max<NTERM>()];
   __shared__ __align__(16) double GyA[kTile];
   __shared__ __align__(16) double GyB[kTile];
   __shared__ float Gx[XB * kTile];
@@ -191,22 +257,10 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
   const int unit = wave >> 1, sub = wave & 1;
   const int r0 = sub * 48;
   const double* hdr = reinterpret_cast<const double*>(ops);
-  const int xs = 2 * pw + 8;           // row stride (16-bit elements) in HBM and LDS
+  const int xs = NTERM * pw + 8;       // row stride (16-bit elements) in HBM and LDS
   const int tile_ch = kTile * xs / 8;  // 16-byte chunks per tile
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-  // this lane's contraction offsets in a stored row.  Chain B (cross
-  // products) reads x [hi | lo] at kb = 32 m + 8 (lane / 16) against y
-  // [lo | hi]; chain A reuses x chunk c < NA (hi wherever kb < pw, and
-  // kb < pw covers all of the hi plane) against y hi, zero elsewhere.
-  // Offsets past a chain's length read the 8 zeros that end every row.
-  int xoff[NB], yoffB[NB], yoffA[NA];
-#pragma unroll
-  for (int m = 0; m < NB; ++m) {
-    const int kb = 32 * m + 8 * lk;
-    xoff[m] = kb < 2 * pw ? kb : 2 * pw;
-    yoffB[m] = kb < pw ? pw + kb : (kb < 2 * pw ? kb - pw : 2 * pw);
-    if (m < NA) yoffA[m] = kb < pw ? kb : 2 * pw;
-  }
+  const Ch ch(pw, lk);
   // copy of entry E's y tile and gaps into the LDS buffers (Y, G): wave w
   // moves the 1 KB pieces w, w + NW, ...; the last wave also moves the gaps
   auto issue = [&](int E, uint16_t* Y, double* G) {
@@ -233,20 +287,15 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
     const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
-    u16x8 xa[TI][NB];
+    u16x8 xa[TI][NX];
     if (fxi >= 0) {
-      const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
-                          (int64_t)(mt * kTile + r0 + li) * xs;
-#pragma unroll
-      for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+      ch.template load_x<TI>(xa, reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
+                            (int64_t)(mt * kTile + r0 + li) * xs, xs);
     } else {
 #pragma unroll
       for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) xa[i][c] = zero;
+        for (int c = 0; c < NX; ++c) xa[i][c] = zero;
     }
     for (int t = threadIdx.x; t < XB * kTile; t += NT) {
       const int u = t / kTile, m = t - (t / kTile) * kTile;
@@ -280,45 +329,7 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
           for (int i = 0; i < TI; ++i)
 #pragma unroll
             for (int j = 0; j < TJP; ++j) acc[i][j] = f4{0, 0, 0, 0};
-#ifdef FEF_SPLIT_SEPARATE
-          f4 accB[TI][TJP];
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJP; ++j) accB[i][j] = f4{0, 0, 0, 0};
-#else
-          f4 (&accB)[TI][TJP] = acc;
-#endif
-          // chain B: the cross products, in chunks of their own
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            u16x8 b[TJP];
-#pragma unroll
-            for (int j = 0; j < TJP; ++j)
-              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoffB[c]);
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-              for (int j = 0; j < TJP; ++j) accB[i][j] = mma16<kFp16>(xa[i][c], b[j], accB[i][j]);
-          }
-          // chain A: the leading products
-#pragma unroll
-          for (int c = 0; c < NA; ++c) {
-            u16x8 b[TJP];
-#pragma unroll
-            for (int j = 0; j < TJP; ++j)
-              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * (jh * TJP + j) * xs + yoffA[c]);
-#pragma unroll
-            for (int i = 0; i < TI; ++i)
-#pragma unroll
-              for (int j = 0; j < TJP; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
-          }
-#ifdef FEF_SPLIT_SEPARATE
-#pragma unroll
-          for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJP; ++j) acc[i][j] += accB[i][j];
-#endif
+          ch.template contract<TI, TJP>(acc, xa, Yb + 16 * jh * TJP * xs, xs);
           part += weighted_tiles_f32<TI, TJP>(acc, Gx + unit * kTile + r0, Gc + 16 * jh * TJP,
                                              lane);
         }
@@ -358,14 +369,16 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
 // epilogue never reads a buffer being refilled.  Each wave leaves its weighted sum in LDS; once
 // both groups have weighted entry e, one lane per unit adds the four wave
 // sums in a fixed order into the entry's partial slot.
-template <bool kFp16, int NA, int NB>
+template <bool kFp16, int NTERM, int N0, int N1, int N2>
 __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
     const FragInfo* __restrict__ frag, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
     int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops,
     int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
   constexpr int XB = 2, NW = 8, NT = 512, NBUF = 3;
-  __shared__ __align__(16) uint16_t Ys[NBUF][kTile * kXsMax];
+  typedef SplitChains<kFp16, NTERM, N0, N1, N2> Ch;
+  constexpr int NX = Ch::NX;
+  __shared__ __align__(16) uint16_t Ys[NBUF][kTile * split_row_max<NTERM>()];
   __shared__ __align__(16) double Gy[NBUF][kTile];
   __shared__ float Gx[XB * kTile];
   __shared__ double red[2][NW];
@@ -375,17 +388,10 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
   const int grp = wave >> 2, unit = (wave >> 1) & 1;
   const int r0 = 48 * (wave & 1), c0 = 48 * grp;
   const double* hdr = reinterpret_cast<const double*>(ops);
-  const int xs = 2 * pw + 8;
+  const int xs = NTERM * pw + 8;
   const int tile_ch = kTile * xs / 8;
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
-  int xoff[NB], yoffB[NB], yoffA[NA];
-#pragma unroll
-  for (int m = 0; m < NB; ++m) {
-    const int kb = 32 * m + 8 * lk;
-    xoff[m] = kb < 2 * pw ? kb : 2 * pw;
-    yoffB[m] = kb < pw ? pw + kb : (kb < 2 * pw ? kb - pw : 2 * pw);
-    if (m < NA) yoffA[m] = kb < pw ? kb : 2 * pw;
-  }
+  const Ch ch(pw, lk);
   // global_load_lds operations one copy puts in flight in this wave
   int nload = wave == NW - 1 ? 1 : 0;
   for (int g = wave; g * 64 < tile_ch; g += NW) ++nload;
@@ -413,20 +419,15 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
     if (ne > 1) issue(e0 + 1, Ys[1], Gy[1]);
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
-    u16x8 xa[3][NB];
+    u16x8 xa[3][NX];
     if (fxi >= 0) {
-      const uint16_t* L = reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
-                          (int64_t)(mt * kTile + r0 + li) * xs;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+      ch.template load_x<3>(xa, reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
+                           (int64_t)(mt * kTile + r0 + li) * xs, xs);
     } else {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) xa[i][c] = zero;
+        for (int c = 0; c < NX; ++c) xa[i][c] = zero;
     }
     for (int t = threadIdx.x; t < XB * kTile; t += NT) {
       const int u = t / kTile, m = t - (t / kTile) * kTile;
@@ -465,30 +466,8 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) acc[i][j] = f4{0, 0, 0, 0};
-          // the cross products first, in chunks of their own; then the
-          // leading products continue the same accumulators
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            u16x8 b[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoffB[c]);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
-          }
-#pragma unroll
-          for (int c = 0; c < NA; ++c) {
-            u16x8 b[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-              b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoffA[c]);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-              for (int j = 0; j < 3; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
-          }
+          // the highest-order products first, the leading ones last
+          ch.template contract<3, 3>(acc, xa, Yb, xs);
         }
       } else {
         // weighting phase
@@ -522,38 +501,37 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
   }
 }
 
-template <bool F16>
-static void launch_split_pp(const fef_plan_s& p, int na, int nb, dim3 grid, hipStream_t st,
-                            const char* o, int prec, int pw, const double* gap,
-                            const Entry* entries, const WorkItem* items, double* partial,
-                            int32_t* head) {
+// Kernel instance for the chain lengths of (nterm, pw), one workgroup per
+// CU: xb = 2 runs the ping-pong kernel, xb = 4 the four-unit kernel (both
+// eight waves).
+template <bool F16, int NTERM>
+static bool launch_split_terms(const fef_plan_s& p, int xb, int pw, dim3 grid, hipStream_t st,
+                               const char* o, int prec, const double* gap, const Entry* entries,
+                               const WorkItem* items, double* partial, int32_t* head) {
   const TileSet& t = p.tiles[prec];
-#define FEF_CHAINS(A, B)                                                                      \
-  if (na == A && nb == B) {                                                                   \
-    hipLaunchKernelGGL((pair_split_pp_kernel<F16, A, B>), grid, dim3(512), 0, st, p.d_frag,   \
-                       t.d_xblocks, entries, items, (int32_t)t.nitems, head, t.d_grp_off, o,  \
-                       prec, pw, gap, partial);                                               \
-    return;                                                                                   \
+  const int n0 = split_chain(0, pw), n1 = split_chain(1, pw);
+  const int n2 = NTERM == 3 ? split_chain(2, pw) : 0;
+#define FEF_CHAINS(A, B, C)                                                                     \
+  if (n0 == A && n1 == B && n2 == C) {                                                          \
+    if (xb == 4)                                                                                \
+      hipLaunchKernelGGL((pair_split_kernel<F16, 4, NTERM, A, B, C>), grid, dim3(512), 0, st,   \
+                         p.d_frag, p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,        \
+                         (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);      \
+    else                                                                                        \
+      hipLaunchKernelGGL((pair_split_pp_kernel<F16, NTERM, A, B, C>), grid, dim3(512), 0, st,   \
+                         p.d_frag, t.d_xblocks, entries, items, (int32_t)t.nitems, head,        \
+                         t.d_grp_off, o, prec, pw, gap, partial);                               \
+    return true;                                                                                \
   }
-  FEF_CHAINS(1, 1) FEF_CHAINS(1, 2) FEF_CHAINS(2, 3) FEF_CHAINS(2, 4) FEF_CHAINS(3, 5)
-#undef FEF_CHAINS
-}
-
-template <bool F16, int XB>
-static void launch_split_chains(const fef_plan_s& p, int na, int nb, dim3 grid, hipStream_t st,
-                                const char* o, int prec, int pw, const double* gap,
-                                const Entry* entries, const WorkItem* items, double* partial,
-                                int32_t* head) {
-  const TileSet& t = p.tiles[prec];
-#define FEF_CHAINS(A, B)                                                                          \
-  if (na == A && nb == B) {                                                                       \
-    hipLaunchKernelGGL((pair_split_kernel<F16, XB, A, B>), grid, dim3(128 * XB), 0, st, p.d_frag, \
-                       p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,                      \
-                       (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);          \
-    return;                                                                                       \
+  if constexpr (NTERM == 2) {
+    FEF_CHAINS(1, 1, 0) FEF_CHAINS(1, 2, 0) FEF_CHAINS(2, 3, 0) FEF_CHAINS(2, 4, 0)
+    FEF_CHAINS(3, 5, 0)
+  } else {
+    FEF_CHAINS(1, 1, 1) FEF_CHAINS(1, 1, 2) FEF_CHAINS(1, 2, 3) FEF_CHAINS(2, 3, 4)
+    FEF_CHAINS(2, 3, 5) FEF_CHAINS(2, 4, 6) FEF_CHAINS(3, 5, 7) FEF_CHAINS(3, 5, 8)
   }
-  FEF_CHAINS(1, 1) FEF_CHAINS(1, 2) FEF_CHAINS(2, 3) FEF_CHAINS(2, 4) FEF_CHAINS(3, 5)
 #undef FEF_CHAINS
+  return false;
 }
 
 hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double* gap,
@@ -561,22 +539,21 @@ hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double
                               double* partial, int32_t* head, int ncu, hipStream_t st) {
   const char* o = static_cast<const char*>(ops);
   const int pw = p.geom[prec].pw;
-  const int na = split_chain_a(pw), nb = split_chain_b(pw);
   const int xb = p.tiles[prec].xb;
   if (pw > 80 || pw < 8 || pw % 8 != 0) return hipErrorInvalidValue;
   if ((p.ops_header & 15) != 0) return hipErrorInvalidValue;  // 16-byte copies
-  // persistent grid, one workgroup per CU: xb = 2 runs the ping-pong kernel
-  // (eight waves), xb = 4 the four-unit kernel (eight waves)
   const dim3 g((unsigned)std::min<int64_t>(ncu, std::max<int64_t>(p.tiles[prec].nitems, 1)));
-  if (prec == FEF_FP16X2) {
-    if (xb == 4) launch_split_chains<true, 4>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_pp<true>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-  } else if (prec == FEF_BF16X2) {
-    if (xb == 4) launch_split_chains<false, 4>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-    else launch_split_pp<false>(p, na, nb, g, st, o, (int)prec, pw, gap, entries, items, partial, head);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  bool ok = false;
+  if (prec == FEF_FP16X2)
+    ok = launch_split_terms<true, 2>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+                                     partial, head);
+  else if (prec == FEF_BF16X2)
+    ok = launch_split_terms<false, 2>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+                                      partial, head);
+  else if (prec == FEF_BF16X3)
+    ok = launch_split_terms<false, 3>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+                                      partial, head);
+  if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

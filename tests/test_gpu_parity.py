@@ -12,7 +12,7 @@ from oracle import fef as ofef
 
 pytestmark = pytest.mark.gpu
 
-PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3}
+PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3, "bf16x3": 4}
 TOL_PAIR_F64 = 1e-9
 
 
@@ -182,7 +182,8 @@ def test_gap_and_nonfinite_flags(torch):
     assert int(ctx2.flags.cpu()[0]) & 2
 
 
-@pytest.mark.parametrize("prec,tol_pair", [("f32", 1e-5), ("bf16x2", 1e-5), ("fp16x2", 1e-6)])
+@pytest.mark.parametrize("prec,tol_pair", [("f32", 1e-5), ("bf16x2", 1e-5), ("fp16x2", 1e-6),
+                                           ("bf16x3", 1e-6)])
 def test_reduced_precision_config0(torch, prec, tol_pair):
     sysm = fefgen.make_system(0)
     ref, ref_tot = ofef.pair_energies(sysm)
@@ -197,7 +198,8 @@ def test_reduced_precision_config0(torch, prec, tol_pair):
 @pytest.mark.parametrize("prec,tiles", [("f64", [(1, 1), (1, 7), (2, 1), (2, 5)]),
                                         ("f32", [(1, 3), (2, 2)]),
                                         ("bf16x2", [(2, 2), (2, 5), (4, 64)]),
-                                        ("fp16x2", [(2, 1), (4, 3)])])
+                                        ("fp16x2", [(2, 1), (4, 3)]),
+                                        ("bf16x3", [(2, 1), (2, 64), (4, 3)])])
 def test_tilings_agree(torch, prec, tiles):
     """Every pair-kernel tiling gives the same pair energies (up to in-tile
     summation order), on ragged and two-class systems."""
@@ -222,7 +224,8 @@ def test_graph_replays_match_eager(torch):
     pool is poisoned before each replay: the pass packs B itself (in its
     first SCF step) before anything reads the pool."""
     import paper_1708_03377_amd as lib
-    for sysm, prec in ((fefgen.make_system(0), "f64"), (two_class_system(), "bf16x2")):
+    for sysm, prec in ((fefgen.make_system(0), "f64"), (two_class_system(), "bf16x2"),
+                       (two_class_system(), "bf16x3")):
         ctx = ctx_for(sysm)
         p = PREC[prec]
         ctx.reset_orbitals(); ctx.scf(3)
