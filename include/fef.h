@@ -280,6 +280,24 @@ fef_status fef_pair_energies_masked(fef_plan plan, const void* ops, const double
                                     double* E2_total, int32_t* flags, void* ws,
                                     size_t ws_bytes, void* stream);
 
+/* Pair energies exactly as fef_pair_energies (same kernels, same tiling,
+ * bitwise the same results), for callers that cannot allocate device memory
+ * or pass a workspace: code under stream capture, tight serving loops,
+ * harnesses that forbid allocation.  The call allocates nothing; the
+ * kernels' scratch (partial-sum slots, queue counters, gap pool) is a
+ * fixed device array of FEF_NOALLOC_SCRATCH_BYTES inside this library, one
+ * per GPU, held until the process ends.  A plan whose FEF_Q_PAIR_WS_BYTES
+ * exceeds that size is rejected with FEF_E_WORKSPACE (nothing enqueued).
+ * Must be called with the plan's device current (else FEF_E_ARG).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race and give wrong results; serialise
+ * them.  The array keeps the last call's contents; each call starts by
+ * clearing the parts that must start at zero. */
+#define FEF_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+fef_status fef_pair_energies_noalloc(fef_plan plan, const void* ops, const double* eps,
+                                     fef_prec prec, double* E2_pair, double* E2_total,
+                                     int32_t* flags, void* stream);
+
 /* ------------------------------------------------------------------------
  * Distant-pair surrogate.  A project addition: the paper has no learned
  * component.  It predicts E2_xy of Eq. ED2 for distant pairs from

@@ -42,7 +42,7 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_fragment_invariants", "fef_pair_features", "fef_column_stats",
                 "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
-                "fef_scf_step_packed", "fef_status_string")
+                "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -109,6 +109,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_surrogate_select.argtypes = [vp, vp, i32, vp, vp, f64, f64, vp, vp, vp]
     lib.fef_pack_coefficients.argtypes = [vp, vp, vp, vp]
     lib.fef_scf_step_packed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.fef_pair_energies_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.fef_status_string.argtypes = [i32]
     lib.fef_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -212,6 +213,12 @@ def fef_pair_energies(plan, ops, eps, prec, E2_pair, E2_total, flags, ws, stream
     _check("fef_pair_energies", load_library().fef_pair_energies(
         plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(E2_pair), _ptr(E2_total), _ptr(flags),
         _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_pair_energies_noalloc(plan, ops, eps, prec, E2_pair, E2_total, flags, stream=None):
+    _check("fef_pair_energies_noalloc", load_library().fef_pair_energies_noalloc(
+        plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(E2_pair), _ptr(E2_total), _ptr(flags),
+        _stream(stream)))
 
 
 def fef_coulomb_field(plan, B, G, D, J, ws, stream=None):

@@ -349,6 +349,9 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     if (e == hipSuccess && !cb.empty()) e = upload(&p->d_chunk_Bp, cb);
   }
   if (e != hipSuccess) { free_plan(p); return FEF_E_HIP; }
+  // set-up of fef_pair_energies_noalloc on this device (an address lookup;
+  // on failure that entry point retries and reports it)
+  (void)noalloc_setup(p->device);
   *out = p;
   return FEF_OK;
 }

@@ -281,6 +281,10 @@ void order_and_orient(fef_plan_s& p);
 hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc);
 void free_tiles(fef::TileSet& t);
 
+// Address of this library's fixed pair-kernel scratch array on `device`
+// (looked up once per device, with that device current).
+hipError_t noalloc_setup(int device);
+
 // Compute units of the current device (queried once, cached).
 int compute_units();
 
