@@ -88,8 +88,10 @@ def pair_issued_flops(sysm, mode: str) -> float:
         k = ((p0 + 3) // 4) * 4
     else:
         pw = ((p0 + 7) // 8) * 8
-        nterm = 3 if mode == "bf16x3" else 2
-        k = sum((((lv + 1) * pw + 31) // 32) * 32 for lv in range(nterm))
+        if mode == "bf16x3":
+            k = sum((((lv + 1) * pw + 31) // 32) * 32 for lv in range(3))
+        else:
+            k = ((3 * pw + 31) // 32) * 32
     return float(np.sum(2.0 * ld[sysm.pair_x] * ld[sysm.pair_y] * k))
 
 
@@ -190,15 +192,15 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
 DEFAULT_MODES = {2: "f64,f32", 3: "f64,f32,bf16x2,fp16x2,bf16x3", 4: "f64,bf16x2,fp16x2,bf16x3"}
 
 
-def bench_surrogate(args, sysm, ctx, lib, torch, st, niter):
+def bench_surrogate(args, sysm, ctx, lib, torch, st, niter, exact_mode):
     """The learned-surrogate pass of the 8000-water workload.  Untimed set-up:
     the ensemble is trained by the library's kernels on the exact FP64 pair
     energies of seeded 1000-water boxes at the same cutoff and density, and
     checked on a held-out box.  Timed step (eager, event-timed): orbital
     reset, niter SCF steps, fragment invariants, ensemble selection, half
-    transform and the exact BF16x2 kernel on every pair the ensemble
-    declines (all pairs below 6 A, every pair whose members disagree by more
-    than the threshold)."""
+    transform and the exact kernel of mode ``exact_mode`` on every pair the
+    ensemble declines (all pairs below 6 A, every pair whose members disagree
+    by more than the threshold)."""
     import fefgen
     from paper_1708_03377_amd import surrogate as sg
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -223,7 +225,7 @@ def bench_surrogate(args, sysm, ctx, lib, torch, st, niter):
             "median_spread_Eh": float(np.median(spread)),
             "frac_spread_below_threshold": float(np.mean(spread <= args.surrogate_threshold))}
     del hctx, Xh, Th
-    prec = lib.PREC["bf16x2"]
+    prec = lib.PREC[exact_mode]
     thr = args.surrogate_threshold
 
     def step():
@@ -265,7 +267,65 @@ def bench_surrogate(args, sysm, ctx, lib, torch, st, niter):
                           "epochs": args.surrogate_epochs, "train_s": round(train_s, 2),
                           "final_loss": hist[-1] if hist else None,
                           "heldout_box": sg.HELDOUT_SEED, "heldout": held,
-                          "exact_kernel": "bf16x2"}}
+                          "exact_kernel": exact_mode}}
+
+
+HBM_PEAK = 8.0e12      # bytes/s
+FP64_PEAK = 78.6e12    # FP64 vector FLOP/s
+
+
+def scf_stage_model(sysm):
+    """Algorithmic work of one packed SCF step (no re-reads counted):
+    moments read the packed coefficients Bp [P][nbf (nbf + 1) / 2] and the
+    weighted densities and write d [P]; the field and Coulomb build read Bp
+    again, every d, G, F0 (and h~) and write F~ [nbf^2]; the eigensolver is
+    counted as 9 n^3 FLOP per matrix (the conventional count of a dense
+    symmetric eigendecomposition with eigenvectors) plus 2 n^2 nocc for the
+    new density."""
+    n = sysm.nbf.astype(np.int64)
+    P = sysm.naux.astype(np.int64)
+    tri = n * (n + 1) // 2
+    bp = 8 * int(np.sum(P * tri))
+    d = 8 * int(np.sum(P))
+    nn = 8 * int(np.sum(n * n))
+    g = 8 * int(sysm.G.size)
+    ht = nn if sysm.htilde is not None else 0
+    return {"moments_bytes": bp + 8 * int(np.sum(tri)) + d,
+            "field_bytes": bp + d + g + nn + ht + nn,
+            "eigh_flops": float(np.sum(9.0 * n ** 3 + 2.0 * n * n * sysm.nocc))}
+
+
+def bench_scf_stages(ctx, lib, sysm, reps: int = 10):
+    """Event-timed stages of eager packed SCF steps (the library records
+    events at the stage boundaries): mean over `reps` steps after one
+    untimed step, each stage against its roofline."""
+    from paper_1708_03377_amd import _fef
+    ctx.reset_orbitals()
+    ctx.scf_step_packed()
+    _fef.fef_plan_stage_timing(ctx.plan, True)
+    rows = []
+    try:
+        for _ in range(reps):
+            ctx.scf_step_packed()
+            rows.append(_fef.fef_plan_stage_ms(ctx.plan))
+    finally:
+        _fef.fef_plan_stage_timing(ctx.plan, False)
+    ms = np.mean(np.asarray(rows), axis=0)
+    m = scf_stage_model(sysm)
+
+    def hbm(nbytes, t):
+        a = nbytes / (t / 1e3)
+        return {"bound": "hbm", "achieved": a / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": a / HBM_PEAK, "bytes_per_launch": nbytes, "ms": round(float(t), 4)}
+    fl = m["eigh_flops"] / (ms[3] / 1e3)
+    return {"steps": reps,
+            "density_ms": round(float(ms[0]), 4),
+            "moments": hbm(m["moments_bytes"], ms[1]),
+            "field_and_coulomb": hbm(m["field_bytes"], ms[2]),
+            "eigensolver": {"bound": "fp64", "achieved": fl / 1e12, "peak": FP64_PEAK / 1e12,
+                            "unit": "TFLOP/s", "frac": fl / FP64_PEAK,
+                            "flops_per_launch": m["eigh_flops"], "ms": round(float(ms[3]), 4)},
+            "step_ms": round(float(np.sum(ms)), 4)}
 
 
 def copy_probe(mib: int):
@@ -365,13 +425,22 @@ def main():
         print(f"[bench] mode {name}: {results[name]['ms_per_step']:.3f} ms/step", file=sys.stderr,
               flush=True)
 
-    if spec.cfg_id == 4:
-        print("[bench] surrogate: training, held-out check, timed passes", file=sys.stderr,
-              flush=True)
-        results["surrogate"] = bench_surrogate(args, sysm, ctx, lib, torch, st, niter)
-
+    print("[bench] SCF stages", file=sys.stderr, flush=True)
+    scf_stages = bench_scf_stages(ctx, lib, sysm)
     ref = results["f64"]
     ref_oracle = oracle_total(spec.name)
+    ref_total = ref_oracle if ref_oracle is not None else ref["E_total"]
+    if spec.cfg_id == 4:
+        # the exact kernel of the surrogate pass: the fastest reduced-precision
+        # mode whose own total meets the bar on this workload (else FP64)
+        passing = [m for m in results if m != "f64" and results[m]["flags"] == 0
+                   and abs(results[m]["E_total"] - ref_total) <= TOTAL_ERR_BAR]
+        exact_mode = min(passing, key=lambda m: results[m]["ms_per_step"]) if passing else "f64"
+        print(f"[bench] surrogate ({exact_mode} exact kernel): training, held-out check, "
+              "timed passes", file=sys.stderr, flush=True)
+        results["surrogate"] = bench_surrogate(args, sysm, ctx, lib, torch, st, niter,
+                                               exact_mode)
+
     modes_out = {}
     for name, r in results.items():
         err_tot = abs(r["E_total"] - ref["E_total"])
@@ -406,8 +475,8 @@ def main():
     head = max(ok, key=lambda m: modes_out[m]["pairs_per_s"]) if ok else "f64"
     h = modes_out[head]
     # the dominant kernel: the exact pair kernel of the headline mode (the
-    # surrogate pass runs the BF16x2 kernel on the pairs it declines)
-    kmode = "bf16x2" if head == "surrogate" else head
+    # surrogate pass runs its exact kernel on the pairs it declines)
+    kmode = modes_out[head]["surrogate"]["exact_kernel"] if head == "surrogate" else head
     hk = modes_out[kmode]
     flops = pair_flops(sysm)
     bound, peak = PEAK[kmode]
@@ -440,6 +509,7 @@ def main():
                      "operand_bytes": pair_operand_bytes(ctx, lib.PREC[kmode])},
         "accuracy_gate": {"bar_Eh": TOTAL_ERR_BAR, "against": "oracle" if ref_oracle is not None
                           else "gpu_f64", "oracle_total": ref_oracle},
+        "scf_roofline": scf_stages,
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],
         "speedup_vs_fp64": h["pairs_per_s"] / modes_out["f64"]["pairs_per_s"],
         "modes": modes_out,

@@ -199,6 +199,19 @@ fef_status fef_scf_step(fef_plan plan, const double* B, const double* G,
                         double* eps, double* D, double* dD_max, int32_t* flags,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* SCF stage timing, for measurement.  While enabled, every fef_scf_step /
+ * fef_scf_step_packed call records five events on its stream: at its start,
+ * after the densities of the input orbitals (Sec. II.A), after the moments
+ * d^y = B^y : D^y, after the field and Coulomb build of Eqs. wc and dp2e,
+ * and after the eigensolver.  fef_plan_stage_ms waits for the last step's
+ * final event and writes the four stage durations (ms) of that step:
+ * ms[0] density, ms[1] moments, ms[2] field + Coulomb build, ms[3]
+ * eigensolver.  Enabling creates the events (once per plan); do not enable
+ * it for steps recorded into a graph.  fef_plan_stage_ms returns FEF_E_ARG
+ * if timing was never enabled. */
+fef_status fef_plan_stage_timing(fef_plan plan, int32_t enable);
+fef_status fef_plan_stage_ms(fef_plan plan, double* ms);
+
 /* Packed coefficients: Bp [P_c][nbf (nbf + 1) / 2] per fragment, the upper
  * triangle (mu <= nu, row-major) of every symmetric slice B^x[P], fragments
  * concatenated (FEF_Q_BPACK_ELEMS doubles, caller-owned).  B must be

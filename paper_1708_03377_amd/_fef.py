@@ -42,7 +42,8 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_fragment_invariants", "fef_pair_features", "fef_column_stats",
                 "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
-                "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_status_string")
+                "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_plan_stage_timing",
+                "fef_plan_stage_ms", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -110,6 +111,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_pack_coefficients.argtypes = [vp, vp, vp, vp]
     lib.fef_scf_step_packed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fef_pair_energies_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.fef_plan_stage_timing.argtypes = [vp, i32]
+    lib.fef_plan_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fef_status_string.argtypes = [i32]
     lib.fef_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -213,6 +216,18 @@ def fef_pair_energies(plan, ops, eps, prec, E2_pair, E2_total, flags, ws, stream
     _check("fef_pair_energies", load_library().fef_pair_energies(
         plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(E2_pair), _ptr(E2_total), _ptr(flags),
         _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_plan_stage_timing(plan, enable: bool):
+    _check("fef_plan_stage_timing", load_library().fef_plan_stage_timing(plan.handle, int(enable)))
+
+
+def fef_plan_stage_ms(plan):
+    """Stage durations (ms) of the last SCF step: density, moments, field +
+    Coulomb build, eigensolver."""
+    out = (ctypes.c_double * 4)()
+    _check("fef_plan_stage_ms", load_library().fef_plan_stage_ms(plan.handle, out))
+    return [float(v) for v in out]
 
 
 def fef_pair_energies_noalloc(plan, ops, eps, prec, E2_pair, E2_total, flags, stream=None):

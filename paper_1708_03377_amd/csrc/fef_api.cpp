@@ -32,6 +32,8 @@ void free_plan(fef_plan_s* p) {
                   p->d_off_tri, p->d_chunk_C, p->d_chunk_Bp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (hipEvent_t& e : p->stage_ev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -40,9 +42,13 @@ OpsGeom geom_of(int prec, int P0) {
     case FEF_F64: return {8, (int)round_up(P0, 4), 0, 1};
     case FEF_F32: return {4, (int)round_up(P0, 4), 0, 1};
     default: {
+      // contraction length the MFMA chains run over
       const int pw = (int)round_up(P0, 8), nt = split_nterm(prec);
       int kp = 0;
-      for (int l = 0; l < nt; ++l) kp += 32 * split_chain(l, pw);
+      if (nt == 2)
+        kp = (int)round_up(3 * pw, 32);
+      else
+        for (int l = 0; l < nt; ++l) kp += 32 * split_chain(l, pw);
       return {2, kp, pw, nt};
     }
   }
@@ -490,17 +496,44 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   // with a carried density the moments kernel clears the maximum that the
   // eigensolver accumulates (no kernel of its own)
   const bool clear_in_moments = Dprev && Bp && p->nfrag > 0;
+  stage_mark(*p, 0, st);
   hipError_t e = !Dprev ? launch_density(*p, C, w.Dold, Bp ? w.Dw : nullptr, dD_max, st)
                  : clear_in_moments ? hipSuccess
                                     : launch_zero_scalar(dD_max, st);
+  stage_mark(*p, 1, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = Bp ? launch_field_packed(*p, Bp, G, w.Dw, F0, htilde, w.F, w.wd, w.wphi, st, B_pack,
                                  Bp_out, clear_in_moments ? dD_max : nullptr)
            : launch_field(*p, B, G, Dold, F0, htilde, w.F, w.wd, w.wphi, st);
+  stage_mark(*p, 3, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, w.F, Dold, C, eps, Dnew, dD_max, flags, w.eigws, st,
                     carry_out ? w.Dw : nullptr);
+  stage_mark(*p, 4, st);
   return hip_status(e);
+}
+
+fef_status fef_plan_stage_timing(fef_plan p, int32_t enable) {
+  if (!p) return FEF_E_ARG;
+  if (enable) {
+    for (hipEvent_t& e : p->stage_ev)
+      if (!e && hipEventCreate(&e) != hipSuccess) return FEF_E_HIP;
+  }
+  p->stage_timing = enable != 0;
+  return FEF_OK;
+}
+
+fef_status fef_plan_stage_ms(fef_plan p, double* ms) {
+  if (!p || !ms) return FEF_E_ARG;
+  if (!p->stage_ev[0]) return FEF_E_ARG;
+  if (hipEventSynchronize(p->stage_ev[kStageMarks - 1]) != hipSuccess) return FEF_E_HIP;
+  for (int i = 0; i + 1 < kStageMarks; ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, p->stage_ev[i], p->stage_ev[i + 1]) != hipSuccess)
+      return FEF_E_HIP;
+    ms[i] = t;
+  }
+  return FEF_OK;
 }
 
 fef_status fef_scf_step(fef_plan p, const double* B, const double* G, const double* F0,

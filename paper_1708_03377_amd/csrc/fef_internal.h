@@ -70,15 +70,13 @@ struct HtTask {
 
 // Operand geometry of a precision mode.
 //   FP64 / FP32: operand stored [kpad][ld], k-major, kpad = round_up(P0, 4).
-//   split modes: operand stored [ld][2 * pw + 8] (row = ia; hi plane, lo
-//   plane, pw = round_up(P0, 8), then 8 zeros so that rows staged in LDS sit
-//   12 banks apart); the leading product runs over round_up(pw, 32) and the
-//   two cross products over round_up(2 pw, 32) contraction indices, kpad
-//   is their sum.
-// Split modes: a value is stored as nterm 16-bit terms (planes 0 = hi,
-// 1 = mid or lo, 2 = lo).  The products of order L (the sum of the two
-// terms' plane indices) form chain L; it runs over (L + 1) pw contraction
-// indices, ceil((L + 1) pw / 32) MFMA chunks of 32.
+//   split modes: operand stored [ld][nterm * pw + 8] (row = ia; the term
+//   planes, pw = round_up(P0, 8) each, then 8 zeros so that rows staged in
+//   LDS sit apart in the banks).  Two terms: the three products run as one
+//   chain over round_up(3 pw, 32) contraction indices.  Three terms: the
+//   products of order L (the sum of the two terms' plane indices) form
+//   chain L over (L + 1) pw indices, ceil((L + 1) pw / 32) MFMA chunks of
+//   32.  kpad is the total contraction length issued.
 __host__ __device__ constexpr int split_chain(int level, int pw) {
   return ((level + 1) * pw + 31) / 32;
 }
@@ -87,12 +85,11 @@ __host__ __device__ constexpr int split_nterm(int prec) { return prec == FEF_BF1
 // Eigensolver workspace (doubles) per fragment with nbf > 48, for the
 // largest such nbf: the Jacobi path keeps V^T and a product matrix
 // (2 (n + 1)^2), the tridiagonal path T (three vectors), the packed
-// reflectors, the eigenvectors of T (rows padded to n + 64 columns) and six
-// vectors of elimination factors per eigenvalue.
+// reflectors and the eigenvectors of T (rows padded to n + 64 columns).
 __host__ __device__ inline int64_t eig_large_slot(int nmax) {
   const int64_t jac = 2 * (int64_t)(nmax + 1) * (nmax + 1);
   const int64_t tri = 3 * (int64_t)nmax + (int64_t)nmax * (nmax + 1) / 2 +
-                      (int64_t)nmax * (nmax + 64) + 6 * (int64_t)nmax * nmax;
+                      (int64_t)nmax * (nmax + 64);
   return jac > tri ? jac : tri;
 }
 // Largest nbf of the tridiagonal (Householder) eigensolver.
@@ -133,8 +130,16 @@ struct Chunk {
   int32_t frag, pad;
 };
 
+// Stage markers of an SCF step: start, after the density, after the
+// moments, after the field and Coulomb build, after the eigensolver.
+constexpr int kStageMarks = 5;
+
 struct fef_plan_s {
   int device = 0;
+  // SCF stage timing (fef_plan_stage_timing): events recorded at the stage
+  // markers of every SCF step while enabled
+  hipEvent_t stage_ev[kStageMarks] = {};
+  bool stage_timing = false;
   int32_t nfrag = 0, nclass = 0, P0 = 0;
   int64_t npair = 0, nslot = 0;
   int32_t max_nbf = 0, max_naux = 0, max_ov = 0;
@@ -284,6 +289,11 @@ void free_tiles(fef::TileSet& t);
 // Address of this library's fixed pair-kernel scratch array on `device`
 // (looked up once per device, with that device current).
 hipError_t noalloc_setup(int device);
+
+// Records stage marker i of an SCF step on st when stage timing is on.
+inline void stage_mark(const fef_plan_s& p, int i, hipStream_t st) {
+  if (p.stage_timing) (void)hipEventRecord(p.stage_ev[i], st);
+}
 
 // Compute units of the current device (queried once, cached).
 int compute_units();

@@ -161,7 +161,8 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
   struct Cand { int32_t rk, y, nt, u, slot; double s; };
   const bool plain = prec == FEF_F64 || prec == FEF_F32;
   const int64_t elem = p.geom[prec].elem_bytes;
-  const int64_t xs = 2 * (int64_t)p.geom[prec].pw + 8;
+  // split modes: stored row length (16-bit elements), nterm planes and 8 zeros
+  const int64_t xs = (int64_t)p.geom[prec].nterm * p.geom[prec].pw + 8;
   for (size_t u0 = 0; u0 < units.size(); u0 += xb) {
     XBlock blk;
     for (int u = 0; u < kMaxXB; ++u) { blk.f[u] = -1; blk.mt[u] = 0; }
@@ -191,7 +192,7 @@ hipError_t build_tiles(fef_plan_s& p, int prec, int xb, int yc) {
       const FragInfo& fy = p.frag[e.y];
       e.ld_y = (int32_t)fy.ld;
       // plain modes: column block nt of [kpad][ld]; split modes: row block
-      // nt of [ld][2 pw + 8]
+      // nt of [ld][nterm pw + 8]
       e.off_R = fy.off_R[prec] + (plain ? (int64_t)e.nt * kTile * elem
                                         : (int64_t)e.nt * kTile * xs * elem);
       e.off_gap = fy.off_gap + (int64_t)e.nt * kTile;

@@ -2,30 +2,39 @@
 // the nucleobase-like solute): canonical orbitals of F~ ascending, Aufbau
 // occupation, the new density and its change, as the Jacobi solvers.
 //
-// Three kernels, one 512-thread workgroup per matrix each, so that every
-// stage has the whole register file to itself:
+// Four kernels; the reduction and the back-transformation run one
+// 512-thread workgroup per matrix, so that they have the whole register
+// file to themselves:
 //   1. eigh_tri_reduce: Householder tridiagonalisation Q^T A Q = T
 //      (A = (F + F^T) / 2).  For k = 0 .. n-3 the reflector
 //      H_k = I - tau_k v_k v_k^T maps the part of row k right of the
 //      diagonal onto its first entry; the trailing block takes the
 //      symmetric rank-2 update A <- A - v w^T - w v^T with p = tau A v,
 //      w = p - (tau / 2)(p . v) v.  A lives in registers, one row per two
-//      lanes (a segment of SEG columns each).
-//   2. eigh_tri_values: the eigenvalues of T by multisection on the Sturm
+//      lanes (lane s of a row holds columns 2 c + s, c < SEG), so that the
+//      columns the shrinking trailing block leaves behind can be skipped in
+//      groups by every lane alike.
+//   2. eigh_tri_bisect: the eigenvalues of T by multisection on the Sturm
 //      count (the number of negative pivots of the LDL^T factorisation of
-//      T - x I): four lanes per eigenvalue count at four interior points,
-//      shrinking the bracket five-fold per round until it is a few ulps of
-//      the eigenvalue (or of ||T|| near zero) wide.  Eigenvalue j is the
+//      T - x I): 16 lanes per eigenvalue count at 16 interior points,
+//      shrinking the bracket 17-fold per round until it is a few ulps of
+//      the eigenvalue (or of ||T|| near zero) wide; 16 eigenvalues per
+//      workgroup, as many workgroups as needed.  Eigenvalue j is the
 //      (j+1)-th smallest, so the order is ascending with ties in index
-//      order.  Then the eigenvectors of T by inverse iteration: Gaussian
-//      elimination with partial pivoting of T - lambda I, three solves
-//      from a fixed pseudo-random start; eigenvalues closer than
-//      1e-3 ||T|| form a cluster that one thread handles in order, each
-//      vector orthogonalised against the cluster's earlier ones after every
-//      solve (modified Gram-Schmidt), a repeated eigenvalue nudged by a few
-//      ulps first.
+//      order.
+//      eigh_tri_vectors: the eigenvectors of T by inverse iteration, one
+//      thread per eigenvalue: Gaussian elimination with partial pivoting of
+//      T - lambda I, three solves from a fixed pseudo-random start;
+//      eigenvalues closer than 1e-3 ||T|| form a cluster that one thread
+//      handles in order, each vector orthogonalised against the cluster's
+//      earlier ones after every solve (modified Gram-Schmidt), a repeated
+//      eigenvalue nudged by a few ulps first.
 //   3. eigh_tri_back: back-transformation C = H_0 H_1 ... H_{n-3} Z, one
-//      eigenvector per two lanes, then C, the density and its change.
+//      eigenvector per two lanes (components interleaved as the columns of
+//      the reduction), four reflectors per step: for z <- H_{r_3} H_{r_2}
+//      H_{r_1} H_{r_0} z (H_{r_0} first) the coefficients are
+//      y_i = tau_i (v_i . z - sum_{j < i} (v_i . v_j) y_j), then
+//      z <- z - sum_i y_i v_i; then C, the density and its change.
 // Eigenvalues are accurate to a few ulps of ||T||; eigenvector residuals
 // and orthogonality are at rounding level times ||T|| / gap.
 #include <algorithm>
@@ -42,6 +51,8 @@ constexpr int kTriThreads = 512;
 constexpr int kTriLanes = 2;  // lanes per row / eigenvector
 constexpr int kTriRowsPerWave = 64 / kTriLanes;
 constexpr int kTriHelper = kTriThreads / 64 - 1;  // the last wave holds no row
+constexpr int kChunk = 4;  // register entries per skipped group (kTriLanes kChunk columns)
+constexpr int kBackBlock = 4;  // reflectors applied per step of the back-transformation
 
 // sum over the two lanes of a row
 __device__ inline double pair_sum(double v) {
@@ -59,19 +70,44 @@ __device__ inline int opaque(int x) {
   return x;
 }
 
+// Reciprocal: the hardware approximation refined by one Newton step
+// (relative error about 1e-16).
+__device__ inline double tri_rcp(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Sturm count: the number of eigenvalues of T below x (negative pivots of
-// T - x I = L D L^T), tiny pivots replaced by -pivmin.
+// T - x I = L D L^T), tiny pivots replaced by -pivmin.  Each pivot is
+// formed with a few ulps of error, which makes the count exact for a T
+// whose off-diagonal squares differ by a few ulps.
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x,
                                   double pivmin) {
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * tri_rcp(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
   }
   return c;
+}
+
+// Bound ||T|| >= max_i |d_i| + |e_{i-1}| + |e_i| and the Gershgorin interval.
+struct TriNorm {
+  double tn, lo, hi, e2max;
+};
+__device__ inline TriNorm tri_norm(const double* dg, const double* ee, int n) {
+  TriNorm t{0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+    t.tn = fmax(t.tn, fabs(dg[i]) + r);
+    t.lo = i == 0 ? dg[i] - r : fmin(t.lo, dg[i] - r);
+    t.hi = i == 0 ? dg[i] + r : fmax(t.hi, dg[i] + r);
+    t.e2max = fmax(t.e2max, ee[i] * ee[i]);
+  }
+  return t;
 }
 
 // Fixed pseudo-random start vector entry in [-1, 1) (a counter hash).
@@ -85,10 +121,9 @@ __device__ inline double start_entry(int j, int i) {
 
 // Per-matrix workspace (doubles, a slot of eig_large_slot(max_n)):
 //   T: d [n], e [n], tau [n]; the reflectors, packed [refl_off(n - 2, n)];
-//   Z [n][n + 64] (row j = eigenvector j of T, zero past n); per eigenvalue
-//   six vectors of elimination factors [n][6 n].
+//   Z [n][n + 64] (row j = eigenvector j of T, zero past n).
 struct TriWs {
-  double *d, *e, *tau, *refl, *Z, *fac;
+  double *d, *e, *tau, *refl, *Z;
 };
 __device__ inline TriWs tri_ws(double* ws_eig, int max_n, int n) {
   TriWs w;
@@ -97,7 +132,6 @@ __device__ inline TriWs tri_ws(double* ws_eig, int max_n, int n) {
   w.tau = w.e + n;
   w.refl = w.tau + n;
   w.Z = w.refl + (n > 2 ? refl_off(n - 2, n) : 0);
-  w.fac = w.Z + (size_t)n * (n + 64);
   return w;
 }
 
@@ -110,6 +144,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
     const double* __restrict__ F, double* __restrict__ ws_eig, int max_n) {
   constexpr int NC = kTriLanes * SEG;  // padded column count
+  static_assert(SEG % kChunk == 0, "whole groups of skipped columns");
   __shared__ double pb[NC];            // p (zero on rows <= k and past n)
   __shared__ double vbuf[2][NC];       // reflector k over every column
   __shared__ double xbuf[NC];          // the row being reduced
@@ -121,8 +156,10 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
   const TriWs W = tri_ws(ws_eig, max_n, n);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = kTriRowsPerWave * wave + lane / kTriLanes, seg = lane % kTriLanes;
-  const int c0 = SEG * seg;
   const bool has_row = row < n;
+  // first row of this wave: a wave whose rows all lie at or above the
+  // reduced row k has no work in step k
+  const int row0 = kTriRowsPerWave * wave;
   const double* Fx = F + fi.off_C;
   double a[SEG];
 #pragma unroll
@@ -130,7 +167,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
   if (has_row) {
 #pragma unroll
     for (int c = 0; c < SEG; ++c) {
-      const int j = opaque(c0) + c;
+      const int j = opaque(seg) + kTriLanes * c;
       const int jc = j < n ? j : n - 1;  // every load in bounds, no branch
       const double v = 0.5 * (Fx[(size_t)row * n + jc] + Fx[(size_t)jc * n + row]);
       a[c] = j < n ? v : 0.0;
@@ -139,7 +176,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
   for (int i = threadIdx.x; i < NC; i += kTriThreads) pb[i] = 0.0;
   if (row == 0) {
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) xbuf[c0 + c] = a[c];
+    for (int c = 0; c < SEG; ++c) xbuf[kTriLanes * c + seg] = a[c];
   }
   __syncthreads();
   for (int k = 0; k + 2 < n; ++k) {
@@ -173,39 +210,52 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
     }
     __syncthreads();
     const double t = s_tau;
+    // v and p vanish on columns <= k: groups of kChunk columns entirely
+    // there are skipped (a test uniform over the workgroup)
+    const bool live = t != 0.0 && row0 + kTriRowsPerWave - 1 > k && row0 < n;
     if (t != 0.0) {
       // p = tau A v over the trailing block (zero on rows <= k), p . v by waves
-      double pr = 0.0;
+      double pr = 0.0, vr = 0.0;
+      if (live) {
 #pragma unroll
-      for (int c = 0; c < SEG; ++c) pr = fma(a[c], vc[c0 + c], pr);
-      pr = row > k ? t * pair_sum(pr) : 0.0;
-      const double vr = has_row ? vc[row] : 0.0;
-      if (has_row && seg == 0) pb[row] = pr;
-      const double pv = wave_sum_dpp(seg == 0 ? pr * vr : 0.0);
+        for (int q = 0; q < SEG / kChunk; ++q)
+          if (kTriLanes * kChunk * (q + 1) - 1 > k)
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+              pr = fma(a[kChunk * q + u], vc[kTriLanes * (kChunk * q + u) + seg], pr);
+        pr = row > k ? t * pair_sum(pr) : 0.0;
+        vr = has_row ? vc[row] : 0.0;
+        if (has_row && seg == 0) pb[row] = pr;
+      }
+      const double pv = live ? wave_sum_dpp(seg == 0 ? pr * vr : 0.0) : 0.0;
       if (lane == 0) wpart[wave] = pv;
       __syncthreads();
-      double s = 0.0;
-      for (int w = 0; w < kTriThreads / 64; ++w) s += wpart[w];
-      const double K = 0.5 * t * s;
+      double sp = 0.0;
+      for (int w = 0; w < kTriThreads / 64; ++w) sp += wpart[w];
+      const double K = 0.5 * t * sp;
       // A <- A - v w^T - w v^T with w = p - K v; rows and columns outside the
       // trailing block have v = p = 0 and keep their values.  Two rounded
       // products and their sum (no contraction): entry (j, r) gets the same
       // two products, so A stays exactly symmetric.
       const double wr = pr - K * vr;
-      {
+      if (live) {
 #pragma clang fp contract(off)
 #pragma unroll
-        for (int c = 0; c < SEG; ++c) {
-          const double vj = vc[c0 + c];
-          const double wj = pb[c0 + c] - K * vj;
-          a[c] -= vr * wj + wr * vj;
-        }
+        for (int q = 0; q < SEG / kChunk; ++q)
+          if (kTriLanes * kChunk * (q + 1) - 1 > k)
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u) {
+              const int c = kChunk * q + u, j = kTriLanes * c + seg;
+              const double vj = vc[j];
+              const double wj = pb[j] - K * vj;
+              a[c] -= vr * wj + wr * vj;
+            }
       }
     }
     // the next row to reduce
     if (row == k + 1) {
 #pragma unroll
-      for (int c = 0; c < SEG; ++c) xbuf[c0 + c] = a[c];
+      for (int c = 0; c < SEG; ++c) xbuf[kTriLanes * c + seg] = a[c];
     }
     __syncthreads();
   }
@@ -214,7 +264,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
     double dd = 0.0, off = 0.0;
 #pragma unroll
     for (int c = 0; c < SEG; ++c) {
-      const int j = opaque(c0) + c;
+      const int j = opaque(seg) + kTriLanes * c;
       if (j == row) dd = a[c];
       if (row == n - 1 && j == n - 2) off = a[c];
     }
@@ -231,177 +281,252 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_reduce_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// 2. eigenvalues (written to eps) and eigenvectors of T
-__global__ __launch_bounds__(kTriThreads) void eigh_tri_values_kernel(
+// 2a. eigenvalues of T (written to eps), kBisPer per workgroup
+constexpr int kBisLanes = 16;  // interior points per eigenvalue and round
+constexpr int kBisThreads = 256;
+constexpr int kBisPer = kBisThreads / kBisLanes;
+
+__global__ __launch_bounds__(kBisThreads) void eigh_tri_bisect_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
     double* __restrict__ eps, double* __restrict__ ws_eig, int max_n) {
-  extern __shared__ double sm[];  // d, e, e^2, lambda [n] each
+  extern __shared__ double sm[];  // d, e, e^2 [n] each
   __shared__ double sc[4];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int n = fi.nbf;
+  const int j0 = blockIdx.y * kBisPer;
+  if (j0 >= n) return;  // uniform over the workgroup
   const TriWs W = tri_ws(ws_eig, max_n, n);
   double* dg = sm;
   double* ee = dg + n;
   double* e2 = ee + n;
-  double* lam = e2 + n;
-  for (int i = threadIdx.x; i < n; i += kTriThreads) {
+  for (int i = threadIdx.x; i < n; i += kBisThreads) {
     dg[i] = W.d[i];
     ee[i] = i + 1 < n ? W.e[i] : 0.0;
+    e2[i] = ee[i] * ee[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tn = 0.0, lo = 0.0, hi = 0.0, e2max = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
-      tn = fmax(tn, fabs(dg[i]) + r);
-      lo = i == 0 ? dg[i] - r : fmin(lo, dg[i] - r);
-      hi = i == 0 ? dg[i] + r : fmax(hi, dg[i] + r);
-      e2[i] = ee[i] * ee[i];
-      e2max = fmax(e2max, e2[i]);
-    }
-    const double pivmin = 1e-290 * fmax(1.0, e2max);
-    const double pad = 2.0 * DBL_EPSILON * tn + 2.0 * pivmin;
-    sc[0] = lo - pad;
-    sc[1] = hi + pad;
-    sc[2] = tn;
+    const TriNorm t = tri_norm(dg, ee, n);
+    const double pivmin = 1e-290 * fmax(1.0, t.e2max);
+    const double pad = 2.0 * DBL_EPSILON * t.tn + 2.0 * pivmin;
+    sc[0] = t.lo - pad;
+    sc[1] = t.hi + pad;
+    sc[2] = t.tn;
     sc[3] = pivmin;
   }
   __syncthreads();
-  {
-    const double pivmin = sc[3];
-    const int m = threadIdx.x & 3;
-    for (int j = threadIdx.x >> 2; j < n; j += kTriThreads / 4) {
-      double lo = sc[0], hi = sc[1];
-      for (int it = 0; it < 80; ++it) {
-        // a bracket of a few ulps of the eigenvalue, or of ||T|| near zero
-        if (!(hi - lo > 2.0 * DBL_EPSILON * (fmax(fabs(lo), fabs(hi)) + sc[2]) + 2.0 * pivmin))
-          break;
-        const double x = lo + (double)(m + 1) * ((hi - lo) * 0.2);
-        const int cnt = sturm_count(dg, e2, n, x, pivmin);
-        // the quad's four points: the new bracket is [last point below the
-        // (j+1)-th eigenvalue, first point at or above it]
-        const int above = cnt >= j + 1;
-        const int m0 = __builtin_amdgcn_mov_dpp(above, 0x00, 0xF, 0xF, false);  // quad lane 0
-        const int m1 = __builtin_amdgcn_mov_dpp(above, 0x55, 0xF, 0xF, false);  // quad lane 1
-        const int m2 = __builtin_amdgcn_mov_dpp(above, 0xAA, 0xF, 0xF, false);  // quad lane 2
-        const int m3 = __builtin_amdgcn_mov_dpp(above, 0xFF, 0xF, 0xF, false);  // quad lane 3
-        const int first = m0 ? 0 : m1 ? 1 : m2 ? 2 : m3 ? 3 : 4;
-        const double w = (hi - lo) * 0.2;
-        const double nlo = first == 0 ? lo : lo + (double)first * w;
-        const double nhi = first == 4 ? hi : lo + (double)(first + 1) * w;
-        lo = nlo;
-        hi = nhi;
-      }
-      if (m == 0) {
-        lam[j] = 0.5 * (lo + hi);
-        eps[fi.off_eps + j] = lam[j];
-      }
+  // eigenvalue j (the (j+1)-th smallest) by a group of kBisLanes lanes: each
+  // counts at one of kBisLanes interior points that cut the bracket into
+  // kBisLanes + 1 equal parts; the new bracket runs from the last point
+  // below the eigenvalue to the first at or above it.  A bracket a few ulps
+  // of the eigenvalue (or of ||T|| near zero) wide ends the search.
+  const int j = j0 + (int)threadIdx.x / kBisLanes, m = (int)threadIdx.x % kBisLanes;
+  const int gsh = (int)(threadIdx.x & 63) & ~(kBisLanes - 1);
+  if (j < n) {  // uniform over each group of lanes
+    const double pivmin = sc[3], tn = sc[2];
+    double lo = sc[0], hi = sc[1];
+    for (int it = 0; it < 100; ++it) {
+      if (!(hi - lo > 2.0 * DBL_EPSILON * (fmax(fabs(lo), fabs(hi)) + tn) + 2.0 * pivmin)) break;
+      const double w = (hi - lo) * (1.0 / (kBisLanes + 1));
+      const double x = lo + (double)(m + 1) * w;
+      const int cnt = sturm_count(dg, e2, n, x, pivmin);
+      const uint64_t ball = __ballot(cnt >= j + 1);
+      const uint32_t g = (uint32_t)(ball >> gsh) & ((1u << kBisLanes) - 1);
+      const int first = g ? __builtin_ctz(g) : kBisLanes;
+      const double nlo = first == 0 ? lo : lo + (double)first * w;
+      const double nhi = first == kBisLanes ? hi : lo + (double)(first + 1) * w;
+      lo = nlo;
+      hi = nhi;
     }
+    if (m == 0) eps[fi.off_eps + j] = 0.5 * (lo + hi);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2b. eigenvectors of T by inverse iteration, one thread per cluster, its
+// work vectors in LDS
+constexpr int kVecThreads = 16;
+constexpr int kVecBatch = 8;  // recurrence steps whose operands load together
+
+// dynamic LDS bytes: d, e, lambda [n]; five work vectors and the row
+// interchange flags [n][kVecThreads], interleaved over the threads
+__host__ __device__ inline size_t vec_lds_bytes(int n) {
+  return (size_t)(3 * n + 5 * n * kVecThreads) * sizeof(double) + (size_t)n * kVecThreads;
+}
+
+__global__ __launch_bounds__(64) void eigh_tri_vectors_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
+    const double* __restrict__ eps, double* __restrict__ ws_eig, int max_n) {
+  extern __shared__ double sm[];
+  __shared__ double s_tn;
+  constexpr int T = kVecThreads;
+  const int f = list[blockIdx.x];
+  const FragInfo fi = frag[f];
+  const int n = fi.nbf;
+  if ((int)blockIdx.y * T >= n) return;  // uniform over the workgroup
+  const TriWs W = tri_ws(ws_eig, max_n, n);
+  double* dg = sm;
+  double* ee = dg + n;
+  double* lam = ee + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    dg[i] = W.d[i];
+    ee[i] = i + 1 < n ? W.e[i] : 0.0;
+    lam[i] = eps[fi.off_eps + i];
   }
   __syncthreads();
-  // inverse iteration, one thread per cluster of close eigenvalues
-  if ((int)threadIdx.x < n) {
-    const int j = threadIdx.x;
-    const int ld = n + 64;
-    const double tn = sc[2];
-    const double ortol = 1e-3 * tn, tiny = DBL_EPSILON * fmax(tn, 1e-300);
-    if (j == 0 || lam[j] - lam[j - 1] > ortol) {
-      int j1 = j;
-      while (j1 + 1 < n && lam[j1 + 1] - lam[j1] <= ortol) ++j1;
-      // this thread's six work vectors, interleaved with the other threads'
-      // (entry i of vector v at (v n + i) n + j), so that threads stepping
-      // through their recurrences together touch neighbouring addresses
-      double* base = W.fac + j;
-      const size_t sv = (size_t)n * n;
-      auto A_ = [&](int i) -> double& { return base[(size_t)i * n]; };           // diagonal of U
-      auto B_ = [&](int i) -> double& { return base[sv + (size_t)i * n]; };      // first superdiagonal
-      auto D_ = [&](int i) -> double& { return base[2 * sv + (size_t)i * n]; };  // second superdiagonal
-      auto L_ = [&](int i) -> double& { return base[3 * sv + (size_t)i * n]; };  // multipliers
-      auto P_ = [&](int i) -> double& { return base[4 * sv + (size_t)i * n]; };  // 1: rows i, i+1 swapped
-      auto x = [&](int i) -> double& { return base[5 * sv + (size_t)i * n]; };   // iterate
-      double prev = 0.0;
-      for (int jj = j; jj <= j1; ++jj) {
-        double lm = lam[jj];
-        if (jj > j && lm - prev < 10.0 * DBL_EPSILON * fabs(lm))
-          lm = prev + 10.0 * DBL_EPSILON * fabs(lm);
-        prev = lm;
-        // T - lm I = P L U with row interchanges between neighbours; the
-        // current row's diagonal and superdiagonal ride in registers
-        double ak = dg[0] - lm, bk = n > 1 ? ee[0] : 0.0;
-        for (int k = 0; k + 1 < n; ++k) {
-          const double ck = ee[k];
-          double ak1 = dg[k + 1] - lm, bk1 = k + 2 < n ? ee[k + 1] : 0.0;
-          if (fabs(ak) >= fabs(ck)) {
-            if (ak == 0.0) ak = tiny;
-            const double l = ck / ak;
-            L_(k) = l;
-            P_(k) = 0.0;
-            D_(k) = 0.0;
-            A_(k) = ak;
-            B_(k) = bk;
-            ak1 -= l * bk;
-          } else {
-            const double l = ak / ck;
-            L_(k) = l;
-            P_(k) = 1.0;
-            A_(k) = ck;
-            B_(k) = ak1;
-            D_(k) = bk1;
-            const double na = bk - l * ak1;
-            bk1 = -l * bk1;
-            ak1 = na;
-          }
-          ak = ak1;
-          bk = bk1;
+  if (threadIdx.x == 0) s_tn = tri_norm(dg, ee, n).tn;
+  __syncthreads();
+  const int t = (int)threadIdx.x;
+  const int j = (int)blockIdx.y * T + t;
+  if (t >= T || j >= n) return;
+  const int ld = n + 64;
+  const double tn = s_tn;
+  const double ortol = 1e-3 * tn, tiny = DBL_EPSILON * fmax(tn, 1e-300);
+  // eigenvalues closer than ortol form a cluster; its first index leads it
+  if (!(j == 0 || lam[j] - lam[j - 1] > ortol)) return;
+  int j1 = j;
+  while (j1 + 1 < n && lam[j1 + 1] - lam[j1] <= ortol) ++j1;
+  // this thread's work vectors, interleaved with the other threads' (entry
+  // i of a vector at i T + t), so that threads stepping through their
+  // recurrences together touch neighbouring banks
+  const size_t sv = (size_t)n * T;
+  double* const ra = lam + n + t;  // 1 / (diagonal of U)
+  double* const ub = ra + sv;      // first superdiagonal of U
+  double* const ud = ub + sv;      // second superdiagonal of U
+  double* const ml = ud + sv;      // multipliers
+  double* const xv = ml + sv;      // iterate
+  unsigned char* const pv = reinterpret_cast<unsigned char*>(lam + n + 5 * sv) + t;  // 1: rows i, i+1 interchanged
+  auto at = [](double* v, int i) -> double& { return v[i * T]; };
+  auto swp = [pv](int i) -> unsigned char& { return pv[i * T]; };
+  double prev = 0.0;
+  for (int jj = j; jj <= j1; ++jj) {
+    double lm = lam[jj];
+    if (jj > j && lm - prev < 10.0 * DBL_EPSILON * fabs(lm))
+      lm = prev + 10.0 * DBL_EPSILON * fabs(lm);
+    prev = lm;
+    // T - lm I = P L U with row interchanges between neighbours; the
+    // current row's diagonal and superdiagonal ride in registers
+    {
+      double ak = dg[0] - lm, bk = n > 1 ? ee[0] : 0.0;
+      for (int k = 0; k + 1 < n; ++k) {
+        const double ck = ee[k];
+        double ak1 = dg[k + 1] - lm, bk1 = k + 2 < n ? ee[k + 1] : 0.0;
+        // pivots below tiny are replaced by +-tiny (as a singular T - lm I
+        // would otherwise stop the solve)
+        auto guard = [tiny](double v) { return fabs(v) < tiny ? (v < 0.0 ? -tiny : tiny) : v; };
+        double piv, b, d, l;
+        if (fabs(ak) >= fabs(ck)) {
+          piv = guard(ak);
+          l = ck * tri_rcp(piv);
+          b = bk;
+          d = 0.0;
+          swp(k) = 0;
+          ak1 -= l * bk;
+        } else {
+          piv = guard(ck);
+          l = ak * tri_rcp(ck);
+          b = ak1;
+          d = bk1;
+          swp(k) = 1;
+          const double na = bk - l * ak1;
+          bk1 = -l * bk1;
+          ak1 = na;
         }
-        A_(n - 1) = ak;
-        B_(n - 1) = 0.0;
-        for (int i = 0; i < n; ++i)
-          if (fabs(A_(i)) < tiny) A_(i) = A_(i) < 0.0 ? -tiny : tiny;
-        for (int i = 0; i < n; ++i) x(i) = start_entry(jj, i);
-        for (int itn = 0; itn < 3; ++itn) {
-          double mx = 0.0;
-          for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x(i)));
-          const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-          for (int i = 0; i < n; ++i) x(i) *= inv;
-          // forward: the row interchanges and multipliers; backward: U
-          double xk = x(0);
-          for (int k = 0; k + 1 < n; ++k) {
-            double x1 = x(k + 1);
-            if (P_(k) != 0.0) {
+        at(ra, k) = tri_rcp(piv);
+        at(ub, k) = b;
+        at(ud, k) = d;
+        at(ml, k) = l;
+        ak = ak1;
+        bk = bk1;
+      }
+      at(ra, n - 1) = tri_rcp(fabs(ak) < tiny ? (ak < 0.0 ? -tiny : tiny) : ak);  // last pivot
+      at(ub, n - 1) = 0.0;
+      at(ud, n - 1) = 0.0;
+    }
+    for (int i = 0; i < n; ++i) at(xv, i) = start_entry(jj, i);
+    for (int itn = 0; itn < 3; ++itn) {
+      double mx = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(at(xv, i)));
+      const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+      // forward: the row interchanges and multipliers, kVecBatch steps'
+      // operands loaded ahead of their serial updates
+      double xk = at(xv, 0) * inv;
+      for (int k0 = 0; k0 + 1 < n; k0 += kVecBatch) {
+        double xl[kVecBatch], ll[kVecBatch];
+        bool pl[kVecBatch];
+#pragma unroll
+        for (int u = 0; u < kVecBatch; ++u) {
+          const int k = min(k0 + u, n - 2);
+          xl[u] = at(xv, k + 1);
+          ll[u] = at(ml, k);
+          pl[u] = swp(k) != 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kVecBatch; ++u) {
+          const int k = k0 + u;
+          if (k + 1 < n) {
+            double x1 = xl[u] * inv;
+            if (pl[u]) {
               const double t = xk;
               xk = x1;
               x1 = t;
             }
-            x1 -= L_(k) * xk;
-            x(k) = xk;
+            x1 -= ll[u] * xk;
+            at(xv, k) = xk;
             xk = x1;
           }
-          x(n - 1) = xk;
-          double x1 = 0.0, x2 = 0.0;  // x(k + 1), x(k + 2)
-          for (int k = n - 1; k >= 0; --k) {
-            const double xv = (x(k) - B_(k) * x1 - D_(k) * x2) / A_(k);
-            x(k) = xv;
-            x2 = x1;
-            x1 = xv;
-          }
-          for (int q = j; q < jj; ++q) {
-            const double* zq = W.Z + (size_t)q * ld;
-            double dot = 0.0;
-            for (int i = 0; i < n; ++i) dot = fma(zq[i], x(i), dot);
-            for (int i = 0; i < n; ++i) x(i) -= dot * zq[i];
-          }
-          double nrm = 0.0;
-          for (int i = 0; i < n; ++i) nrm = fma(x(i), x(i), nrm);
-          const double r = 1.0 / sqrt(nrm);
-          for (int i = 0; i < n; ++i) x(i) *= r;
         }
-        double* zj = W.Z + (size_t)jj * ld;
-        for (int i = 0; i < n; ++i) zj[i] = x(i);
-        for (int i = n; i < ld; ++i) zj[i] = 0.0;
       }
+      at(xv, n - 1) = xk;
+      // backward: U x = y
+      double x1 = 0.0, x2 = 0.0;  // x(k + 1), x(k + 2)
+      for (int k0 = n - 1; k0 >= 0; k0 -= kVecBatch) {
+        double yl[kVecBatch], bl[kVecBatch], dl[kVecBatch], rl[kVecBatch];
+#pragma unroll
+        for (int u = 0; u < kVecBatch; ++u) {
+          const int k = max(k0 - u, 0);
+          yl[u] = at(xv, k);
+          bl[u] = at(ub, k);
+          dl[u] = at(ud, k);
+          rl[u] = at(ra, k);
+        }
+#pragma unroll
+        for (int u = 0; u < kVecBatch; ++u) {
+          const int k = k0 - u;
+          if (k >= 0) {
+            const double xv_ = (yl[u] - bl[u] * x1 - dl[u] * x2) * rl[u];
+            at(xv, k) = xv_;
+            x2 = x1;
+            x1 = xv_;
+          }
+        }
+      }
+      for (int q = j; q < jj; ++q) {
+        const double* zq = W.Z + (size_t)q * ld;
+        // four partial sums (added in a fixed order) break the chain
+        double d4[4] = {0.0, 0.0, 0.0, 0.0};
+        int i = 0;
+        for (; i + 4 <= n; i += 4)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) d4[u] = fma(zq[i + u], at(xv, i + u), d4[u]);
+        for (; i < n; ++i) d4[0] = fma(zq[i], at(xv, i), d4[0]);
+        const double dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+#pragma unroll 8
+        for (int i2 = 0; i2 < n; ++i2) at(xv, i2) -= dot * zq[i2];
+      }
+      double nrm = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < n; ++i) nrm = fma(at(xv, i), at(xv, i), nrm);
+      const double r = 1.0 / sqrt(nrm);
+#pragma unroll 8
+      for (int i = 0; i < n; ++i) at(xv, i) *= r;
     }
+    double* zj = W.Z + (size_t)jj * ld;
+#pragma unroll 8
+    for (int i = 0; i < n; ++i) zj[i] = at(xv, i);
+    for (int i = n; i < ld; ++i) zj[i] = 0.0;
   }
 }
 
@@ -415,7 +540,8 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
     double* __restrict__ ws_eig, int max_n) {
   constexpr int NC = kTriLanes * SEG;
   extern __shared__ double sm[];  // the packed reflectors, later the occupied block
-  __shared__ double vbuf[2][NC];
+  __shared__ double vbuf[2][kBackBlock][NC];  // a block of expanded reflectors
+  __shared__ double gbuf[2][kBackBlock * kBackBlock];  // tau_i, v_i . v_j (i > j)
   __shared__ double red[kTriThreads / 64];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
@@ -423,48 +549,102 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
   const TriWs W = tri_ws(ws_eig, max_n, n);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = kTriRowsPerWave * wave + lane / kTriLanes, seg = lane % kTriLanes;
-  const int c0 = SEG * seg;
   const bool has_row = row < n;
   const int nrefl = n > 2 ? refl_off(n - 2, n) : 0;
   for (int i = threadIdx.x; i < nrefl; i += kTriThreads) sm[i] = W.refl[i];
-  // z[c]: component c0 + c of eigenvector `row` of T
+  // z[c]: component 2 c + seg of eigenvector `row` of T
   double z[SEG];
 #pragma unroll
   for (int c = 0; c < SEG; ++c) z[c] = 0.0;
   if (has_row) {
-    const double* zr = W.Z + (size_t)row * (n + 64) + c0;
+    const double* zr = W.Z + (size_t)row * (n + 64) + seg;
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) z[c] = zr[c];
+    for (int c = 0; c < SEG; ++c) z[c] = zr[kTriLanes * c];
   }
   __syncthreads();
-  // reflector k expanded over every column (zeros outside k+1 .. n-1) by
-  // the helper wave into the buffer of its parity, one step ahead
-  auto expand = [&](int k) {
-    const double* vk = sm + refl_off(k, n) - (k + 1);
-    double* dst = vbuf[k & 1];
-    for (int j = lane; j < NC; j += 64) dst[j] = (j > k && j < n) ? vk[j] : 0.0;
-  };
-  if (wave == kTriHelper && n >= 3) expand(n - 3);
-  __syncthreads();
-  for (int k = n - 3; k >= 0; --k) {
-    if (wave == kTriHelper && k >= 1) expand(k - 1);
-    const double t = W.tau[k];
-    const double* v = vbuf[k & 1];
-    double dot = 0.0;
+  // Block b holds reflectors r_i = k0 - i, i < kBackBlock, k0 = n - 3 -
+  // kBackBlock b, applied in the order r_0, r_1, ... (H_{r_0} first); a
+  // reflector index below 0 is a zero vector with tau = 0.  The helper
+  // wave expands block b + 1 (zeros outside r_i + 1 .. n - 1) and its Gram
+  // entries g_ij = v_i . v_j into the buffers of its parity one step ahead.
+  const int nb = n >= 3 ? (n - 2 + kBackBlock - 1) / kBackBlock : 0;
+  auto expand = [&](int b) {
+    const int k0 = n - 3 - kBackBlock * b;
+    double* dst = &vbuf[b & 1][0][0];
+    double* g = gbuf[b & 1];
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) dot = fma(v[c0 + c], z[c], dot);
-    dot = t * pair_sum(dot);
-    // read v again rather than keep SEG values of it live next to z
+    for (int i = 0; i < kBackBlock; ++i) {
+      const int k = k0 - i;
+      const double* vk = sm + (k >= 0 ? refl_off(k, n) - (k + 1) : 0);
+      for (int j = lane; j < NC; j += 64)
+        dst[i * NC + j] = (k >= 0 && j > k && j < n) ? vk[j] : 0.0;
+    }
+    // the expansion above is this wave's own LDS writes: in order for its
+    // reads below
+#pragma unroll
+    for (int i = 1; i < kBackBlock; ++i)
+#pragma unroll
+      for (int jj = 0; jj < i; ++jj) {
+        double d = 0.0;
+        for (int j = lane; j < NC; j += 64) d = fma(dst[i * NC + j], dst[jj * NC + j], d);
+        d = wave_sum_dpp(d);
+        if (lane == 0) g[i * kBackBlock + jj] = d;
+      }
+    if (lane < kBackBlock) {
+      const int k = k0 - lane;
+      g[lane * kBackBlock + lane] = k >= 0 ? W.tau[k] : 0.0;
+    }
+  };
+  if (wave == kTriHelper && nb > 0) expand(0);
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    if (wave == kTriHelper && b + 1 < nb) expand(b + 1);
+    const int kmin = n - 3 - kBackBlock * b - (kBackBlock - 1);  // every v_i vanishes on <= kmin
+    const double* v = &vbuf[b & 1][0][0];
+    const double* g = gbuf[b & 1];
+    // w_i = v_i . z; groups of kChunk components entirely at or below kmin
+    // are skipped (a test uniform over the workgroup)
+    double w[kBackBlock];
+#pragma unroll
+    for (int i = 0; i < kBackBlock; ++i) w[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < SEG / kChunk; ++q)
+      if (kTriLanes * kChunk * (q + 1) - 1 > kmin)
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const int c = kChunk * q + u, j = kTriLanes * c + seg;
+#pragma unroll
+          for (int i = 0; i < kBackBlock; ++i) w[i] = fma(v[i * NC + j], z[c], w[i]);
+        }
+    // y_i = tau_i (w_i - sum_{j < i} g_ij y_j): H_{r_0} first, then H_{r_1}, ...
+    double y[kBackBlock];
+#pragma unroll
+    for (int i = 0; i < kBackBlock; ++i) {
+      double a = pair_sum(w[i]);
+#pragma unroll
+      for (int jj = 0; jj < i; ++jj) a -= g[i * kBackBlock + jj] * y[jj];
+      y[i] = g[i * kBackBlock + i] * a;
+    }
+    // read v again rather than keep its values live next to z
     asm volatile("" ::: "memory");
 #pragma unroll
-    for (int c = 0; c < SEG; ++c) z[c] -= dot * v[c0 + c];
+    for (int q = 0; q < SEG / kChunk; ++q)
+      if (kTriLanes * kChunk * (q + 1) - 1 > kmin)
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+          const int c = kChunk * q + u, j = kTriLanes * c + seg;
+          double zc = z[c];
+#pragma unroll
+          for (int i = 0; i < kBackBlock; ++i) zc -= y[i] * v[i * NC + j];
+          z[c] = zc;
+        }
     __syncthreads();
   }
   // C column `row` (ascending eigenvalue order)
   if (has_row) {
 #pragma unroll
     for (int c = 0; c < SEG; ++c) {
-      const int i = opaque(c0) + c;
+      const int i = opaque(seg) + kTriLanes * c;
       if (i < n) C[fi.off_C + (size_t)i * n + row] = z[c];
     }
   }
@@ -475,7 +655,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
   if (has_row && row < nocc) {
 #pragma unroll
     for (int c = 0; c < SEG; ++c) {
-      const int i = opaque(c0) + c;
+      const int i = opaque(seg) + kTriLanes * c;
       if (i < n) Co[row * n + i] = z[c];
     }
   }
@@ -507,9 +687,22 @@ hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* D
   const size_t lds_back =
       std::max<size_t>((size_t)refl_off(std::max(nmax - 2, 0), nmax), (size_t)omax * nmax) *
       sizeof(double);
-  const size_t lds_val = 4 * (size_t)nmax * sizeof(double);
+  const size_t lds_bis = 3 * (size_t)nmax * sizeof(double);
+  const size_t lds_vec = vec_lds_bytes(nmax);
+  if (lds_vec > 150 * 1024) return hipErrorInvalidValue;
+  {
+    static bool configured = false;
+    if (!configured) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_tri_vectors_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      (void)hipGetLastError();
+      configured = true;
+    }
+  }
   if (lds_back > 140 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)p.eig_large.size());
+  const dim3 grid_bis(grid.x, (unsigned)((nmax + kBisPer - 1) / kBisPer));
+  const dim3 grid_vec(grid.x, (unsigned)((nmax + kVecThreads - 1) / kVecThreads));
 #define FEF_TRI(S)                                                                             \
   {                                                                                            \
     static bool configured = false;                                                            \
@@ -521,7 +714,9 @@ hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* D
     }                                                                                          \
     hipLaunchKernelGGL(eigh_tri_reduce_kernel<S>, grid, dim3(kTriThreads), 0, st, p.d_frag,    \
                        p.d_eig_large, F, ws_eig, nmax);                                        \
-    hipLaunchKernelGGL(eigh_tri_values_kernel, grid, dim3(kTriThreads), lds_val, st, p.d_frag, \
+    hipLaunchKernelGGL(eigh_tri_bisect_kernel, grid_bis, dim3(kBisThreads), lds_bis, st,       \
+                       p.d_frag, p.d_eig_large, eps, ws_eig, nmax);                            \
+    hipLaunchKernelGGL(eigh_tri_vectors_kernel, grid_vec, dim3(64), lds_vec, st, p.d_frag,     \
                        p.d_eig_large, eps, ws_eig, nmax);                                      \
     hipLaunchKernelGGL(eigh_tri_back_kernel<S>, grid, dim3(kTriThreads), lds_back, st,        \
                        p.d_frag, p.d_eig_large, Dold, C, eps, Dnew, dD_max, flags, ws_eig,     \

@@ -676,6 +676,7 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
   else
     hipLaunchKernelGGL(moments_packed_kernel<false>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
                        p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr, nqb, zero_out);
+  stage_mark(p, 2, st);
   const int etot = p.naux_cls_off.back();
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   if (small_fragments(p)) {
@@ -727,6 +728,7 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G, c
                         double* ws_phi, hipStream_t st) {
   hipLaunchKernelGGL(moments_kernel, dim3(p.nfrag, (p.max_naux + 4 * kMomQ - 1) / (4 * kMomQ)),
                      dim3(256), 0, st, p.d_frag, B, D, ws_d);
+  stage_mark(p, 2, st);
   const int etot = p.naux_cls_off.back();
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,

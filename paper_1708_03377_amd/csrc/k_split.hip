@@ -7,19 +7,21 @@
 // per ia) holds the term planes t0 | t1 [| t2], each pw = round_up(P0, 8)
 // wide, then 8 zeros.  The product keeps the terms of order up to nterm - 1
 // (order = the sum of the two terms' plane indices): order 0 is t0 t0',
-// order 1 is t0 t1' + t1 t0', order 2 is t0 t2' + t1 t1' + t2 t0'.  The
-// products of one order form one MFMA chain: x reads the planes 0..L
-// concatenated, y the same planes in reverse order, over (L + 1) pw
-// contraction indices padded to chunks of 32 with the row's zero tail.  The
-// chains run from the highest order to the lowest into one FP32
-// accumulator, so that no MFMA instruction adds a small high-order product
-// next to a leading one: within one instruction the hardware drops the low
-// bits of addends far below the largest one.  pw is a multiple of 8, so the
+// order 1 is t0 t1' + t1 t0', order 2 is t0 t2' + t1 t1' + t2 t0'.
+// Two terms: the three products run as one MFMA chain over a concatenated
+// contraction axis of 3 pw indices (x planes t0, t0, t1 against y planes
+// t0, t1, t0), padded to chunks of 32 with the row's zero tail.  Three
+// terms: the products of one order form one chain (x reads the planes
+// 0..L concatenated, y the same planes in reverse order, over (L + 1) pw
+// indices), and the chains run from the highest order to the lowest into
+// one FP32 accumulator, so that x needs only the 3 pw indices of its row in
+// registers.  In both forms pw is a multiple of 8, so the
 // 8 contraction indices a lane feeds one MFMA never straddle two planes.
 // FP16 operands carry a per-fragment power-of-two scale that places each
 // operand's largest value in [2^13, 2^14), keeping the low terms out of the
 // subnormal range; the scales are undone exactly in FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "fef_internal.h"
 #include "fef_device.h"
@@ -160,6 +162,48 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// The two-term contraction as one chain for a lane with k-group lk: chunk
+// m covers kk = 32 m + 8 lk; segment s = kk / pw of the concatenated axis
+// pairs x plane (0, 0, 1)[s] with y plane (0, 1, 0)[s] at offset kk - s pw
+// within the plane, and kk >= 3 pw reads the row's zero tail.
+template <bool kFp16, int NC>
+struct SplitChain2 {
+  static constexpr int kNterm = 2;
+  static constexpr int NX = NC;
+  int xoff[NC], yoff[NC];
+  __device__ __forceinline__ SplitChain2(int pw, int lk) {
+    const int tail = 2 * pw;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const int kk = 32 * m + 8 * lk;
+      const int sg = kk / pw, in = kk - sg * pw;
+      xoff[m] = kk < 3 * pw ? (sg == 2 ? pw : 0) + in : tail;
+      yoff[m] = kk < 3 * pw ? (sg == 1 ? pw : 0) + in : tail;
+    }
+  }
+  template <int TI>
+  __device__ __forceinline__ void load_x(u16x8 (&xa)[TI][NX], const uint16_t* L, int xs) const {
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+      for (int c = 0; c < NX; ++c) xa[i][c] = *reinterpret_cast<const u16x8*>(L + 16 * i * xs + xoff[c]);
+  }
+  template <int TI, int TJ>
+  __device__ __forceinline__ void contract(f4 (&acc)[TI][TJ], const u16x8 (&xa)[TI][NX],
+                                           const uint16_t* Yb, int xs) const {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      u16x8 b[TJ];
+#pragma unroll
+      for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * xs + yoff[c]);
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][c], b[j], acc[i][j]);
+    }
+  }
+};
+
 // The chains of one split contraction for a lane with k-group lk: x chunk m
 // reads the stored row at kk = 32 m + 8 lk (the planes concatenated); the
 // chain of order L pairs it with y plane L - i, i = kk / pw, at the same
@@ -168,6 +212,7 @@ __device__ inline f4 mma16(u16x8 a, u16x8 b, f4 c) {
 // terms); NX = the chunks of the highest order, which cover every x chunk.
 template <bool kFp16, int NTERM, int N0, int N1, int N2>
 struct SplitChains {
+  static constexpr int kNterm = NTERM;
   static constexpr int NX = NTERM == 3 ? N2 : N1;
   int xoff[NX], y0[N0], y1[N1], y2[N2 > 0 ? N2 : 1];
   __device__ __forceinline__ SplitChains(int pw, int lk) {
@@ -224,15 +269,20 @@ constexpr int split_row_max() { return NTERM * 80 + 8; }
 // threads; XB = 2 runs two workgroups per CU, whose barriers are
 // independent, so one workgroup's FP32 epilogue overlaps the other's MFMA
 // chains on the same SIMD).  Every wave owns 48 x rows x 96 y columns: its
-// MFMA A fragments (rows [hi|lo] of W^x, all NCH contraction chunks) stay in
-// registers for the whole item; the streamed y tiles (rows [hi|lo] of B^y)
-// and their gaps are copied from global memory straight into one of two LDS
-// buffers (global_load_lds, 16 bytes per lane) while the other buffer is
-// contracted.  The two buffers are separate LDS arrays, so the compiler
-// knows that reads of the current one never wait for the copy into the next.
-// MFMA operand lane layout (16x16x32): row (or column) = lane % 16,
-// contraction indices 8 (lane / 16) .. +7.
-template <bool kFp16, int XB, int NTERM, int N0, int N1, int N2>
+// MFMA A fragments (rows of W^x, all contraction chunks) stay in registers
+// for the whole item; the streamed y tiles (rows of B^y), their gaps and
+// the y operand's scale are copied from global memory straight into a ring
+// of NBUF LDS buffers (global_load_lds, 16 bytes per lane) while an earlier
+// buffer is contracted: the copy of entry e + NBUF - 1 is issued at the
+// start of entry e into the buffer entry e - 1 left, and at the end of
+// entry e only entry e + 1's copy is waited for.  Buffer indices are
+// compile-time constants (the entry loop is unrolled over the ring), so the
+// compiler sees that reads of the current buffer never wait for a copy into
+// another.  Nothing in the entry loop is loaded through the vector memory
+// path except the copies, so no wait on a loaded value drains the copies
+// in flight.  MFMA operand lane layout (16x16x32): row (or column) =
+// lane % 16, contraction indices 8 (lane / 16) .. +7.
+template <bool kFp16, int XB, class Ch>
 __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     const FragInfo* __restrict__ frag, const PairInfo* __restrict__ pairs,
     const int32_t* __restrict__ slot_pair, const XBlock* __restrict__ xblocks,
@@ -241,12 +291,13 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
   constexpr int NT = 128 * XB, NW = 2 * XB;
   constexpr int TI = 3, TJ = 6, TJP = 3;
-  typedef SplitChains<kFp16, NTERM, N0, N1, N2> Ch;
+  constexpr int NTERM = Ch::kNterm;
   constexpr int NX = Ch::NX;
-  __shared__ __align__(16) uint16_t YsA[kTile * split_row_max<NTERM>()];
-  __shared__ __align__(16) uint16_t YsB[kTile * split_row_max<NTERM>()];
-  __shared__ __align__(16) double GyA[kTile];
-  __shared__ __align__(16) double GyB[kTile];
+  // ring depth: two buffers for two workgroups per CU, else as many as fit
+  constexpr int NBUF = XB == 2 ? 2 : (NTERM == 3 ? 3 : 4);
+  constexpr int GL = kTile + 2;  // gaps, then the y operand's two scales
+  __shared__ __align__(16) uint16_t Ys[NBUF][kTile * split_row_max<NTERM>()];
+  __shared__ __align__(16) double Gy[NBUF][GL];
   __shared__ float Gx[XB * kTile];
   __shared__ double red[2][NW];
   __shared__ int32_t s_item;
@@ -261,8 +312,12 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
   const int tile_ch = kTile * xs / 8;  // 16-byte chunks per tile
   const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
   const Ch ch(pw, lk);
-  // copy of entry E's y tile and gaps into the LDS buffers (Y, G): wave w
-  // moves the 1 KB pieces w, w + NW, ...; the last wave also moves the gaps
+  // global_load_lds operations one copy puts in flight in this wave
+  int nload = wave == NW - 1 ? 1 : 0;
+  for (int g = wave; g * 64 < tile_ch; g += NW) ++nload;
+  // copy of entry E's y tile, gaps and scales into the LDS buffer (Y, G):
+  // wave w moves the 1 KB pieces w, w + NW, ...; lanes 0-47 of the last wave
+  // move the gaps and its lane 48 the scale pair hdr[2 y], hdr[2 y + 1]
   auto issue = [&](int E, uint16_t* Y, double* G) {
     const char* src = ops + entries[E].off_R;
     for (int g = wave; g * 64 < tile_ch; g += NW) {
@@ -271,19 +326,23 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
         __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 16 * (int64_t)c),
                                          (lds_void_t*)(Y + g * 512), 16, 0, 0);
     }
-    if (wave == NW - 1 && lane < kTile / 2)
-      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gap + entries[E].off_gap + 2 * lane),
-                                       (lds_void_t*)(G), 16, 0, 0);
+    if (wave == NW - 1 && lane <= kTile / 2) {
+      const double* gsrc = lane < kTile / 2 ? gap + entries[E].off_gap + 2 * lane
+                                            : hdr + 2 * entries[E].y;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gsrc), (lds_void_t*)(G), 16, 0, 0);
+    }
   };
   for (;;) {
     if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
-    const int32_t it = s_item;
+    const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
     if (ne == 0) continue;  // an item emptied by a pair mask
-    issue(e0, YsA, GyA);
+#pragma unroll
+    for (int b = 0; b + 1 < NBUF; ++b)
+      if (b < ne) issue(e0 + b, Ys[b], Gy[b]);
     const int fxi = xblocks[xbid].f[unit];
     const int mt = xblocks[xbid].mt[unit];
     const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
@@ -304,21 +363,18 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    const int end = e0 + ne;
-    // one entry on buffer (Yc, Gc) while entry e + 1 is copied into (Yn, Gn)
-    auto entry = [&](int e, int cur, const uint16_t* Yc, const double* Gc, uint16_t* Yn,
-                     double* Gn) {
+    // entry el (local index) on ring buffer B; issues entry el + NBUF - 1's
+    // copy into the buffer entry el - 1 left
+    auto entry = [&](auto Bc, int el) {
+      constexpr int B = decltype(Bc)::value, BN = (B + NBUF - 1) % NBUF;
+      const int e = e0 + el;
       const int slot = entries[e].slot[unit];
-      double pscale = 0.0;
-      if (sub == 0 && slot >= 0) {
-        const double s = entries[e].s[unit];
-        const double sc = sx * hdr[2 * entries[e].y + 1];
-        pscale = 4.0 * s * s * sc * sc;
-      }
-      if (e + 1 < end) issue(e + 1, Yn, Gn);
+      if (el + NBUF - 1 < ne) issue(e + NBUF - 1, Ys[BN], Gy[BN]);
+      const double* Gc = Gy[B];
+      const double sy = Gc[kTile + 1];
       double mine = 0.0;
       if (slot >= 0) {
-        const uint16_t* Yb = Yc + li * xs;
+        const uint16_t* Yb = Ys[B] + li * xs;
         // the wave's TJ column tiles in passes of TJP, so that TI x TJP
         // independent accumulators stay live over the whole contraction
         double part = 0.0;
@@ -335,17 +391,26 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
         }
         mine = wave_sum_dpp(part);
       }
-      if (lane == 0) red[cur][wave] = mine;
-      // the copy into the next buffer has landed (this wave's part), and
-      // after the barrier every wave's part has
-      __builtin_amdgcn_s_waitcnt(0);
+      if (lane == 0) red[el & 1][wave] = mine;
+      // entry el + 1's copy has landed (this wave's part; after the
+      // barrier, every wave's part); later copies may stay in flight
+      const int later = min(NBUF - 2, ne - el - 2);
+      if (later > 0)
+        wait_vm_upto(later * nload);
+      else
+        __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
-      if (sub == 0 && lane == 0 && slot >= 0)
-        partial[slot] = pscale * (red[cur][wave] + red[cur][wave + 1]);
+      if (sub == 0 && lane == 0 && slot >= 0) {
+        const double s = entries[e].s[unit];
+        const double sc = sx * sy;
+        partial[slot] = 4.0 * s * s * sc * sc * (red[el & 1][wave] + red[el & 1][wave + 1]);
+      }
     };
-    for (int e = e0; e < end; e += 2) {
-      entry(e, 0, YsA, GyA, YsB, GyB);
-      if (e + 1 < end) entry(e + 1, 1, YsB, GyB, YsA, GyA);
+    for (int el = 0; el < ne; el += NBUF) {
+      entry(std::integral_constant<int, 0>{}, el);
+      if (el + 1 < ne) entry(std::integral_constant<int, 1 % NBUF>{}, el + 1);
+      if (NBUF > 2 && el + 2 < ne) entry(std::integral_constant<int, 2 % NBUF>{}, el + 2);
+      if (NBUF > 3 && el + 3 < ne) entry(std::integral_constant<int, 3 % NBUF>{}, el + 3);
     }
   }
 }
@@ -369,17 +434,18 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
 // epilogue never reads a buffer being refilled.  Each wave leaves its weighted sum in LDS; once
 // both groups have weighted entry e, one lane per unit adds the four wave
 // sums in a fixed order into the entry's partial slot.
-template <bool kFp16, int NTERM, int N0, int N1, int N2>
+template <bool kFp16, class Ch>
 __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
     const FragInfo* __restrict__ frag, const XBlock* __restrict__ xblocks,
     const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
     int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops,
     int prec, int pw, const double* __restrict__ gap, double* __restrict__ partial) {
   constexpr int XB = 2, NW = 8, NT = 512, NBUF = 3;
-  typedef SplitChains<kFp16, NTERM, N0, N1, N2> Ch;
+  constexpr int NTERM = Ch::kNterm;
   constexpr int NX = Ch::NX;
   __shared__ __align__(16) uint16_t Ys[NBUF][kTile * split_row_max<NTERM>()];
-  __shared__ __align__(16) double Gy[NBUF][kTile];
+  __shared__ __align__(16) double Gy[NBUF][kTile + 2];  // gaps, then the y scales
+  __shared__ double ysc[2];  // y scale of the entries being finished
   __shared__ float Gx[XB * kTile];
   __shared__ double red[2][NW];
   __shared__ int32_t s_item;
@@ -403,14 +469,16 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
         __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 16 * (int64_t)c),
                                          (lds_void_t*)(Y + g * 512), 16, 0, 0);
     }
-    if (wave == NW - 1 && lane < kTile / 2)
-      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gap + entries[E].off_gap + 2 * lane),
-                                       (lds_void_t*)(G), 16, 0, 0);
+    if (wave == NW - 1 && lane <= kTile / 2) {
+      const double* gsrc = lane < kTile / 2 ? gap + entries[E].off_gap + 2 * lane
+                                            : hdr + 2 * entries[E].y;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gsrc), (lds_void_t*)(G), 16, 0, 0);
+    }
   };
   for (;;) {
     if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
     __syncthreads();
-    const int32_t it = s_item;
+    const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it < 0 || it >= nitems) break;
     const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
@@ -434,16 +502,23 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
       const int f = xblocks[xbid].f[u];
       Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
     }
+    // x scale of thread u's unit (u < XB finishes unit u's slots)
+    const int fu = threadIdx.x < XB ? xblocks[xbid].f[threadIdx.x] : -1;
+    const double sxu = fu >= 0 ? hdr[2 * fu] : 0.0;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // partial slot of entry E for unit u, from the four wave sums of
-    // the unit in a fixed order
+    // the unit in a fixed order; the scales come from registers and LDS, so
+    // no vector load waits on the copies in flight
     auto finish = [&](int el, int u) {
       const int E = e0 + el;
-      const int slot = entries[E].slot[u];
+      // both units' metadata through uniform (scalar) loads
+      const int sl0 = entries[E].slot[0], sl1 = entries[E].slot[1];
+      const double s0 = entries[E].s[0], s1 = entries[E].s[1];
+      const int slot = u == 0 ? sl0 : sl1;
       if (slot < 0) return;
-      const double s = entries[E].s[u];
-      const double sc = hdr[2 * xblocks[xbid].f[u]] * hdr[2 * entries[E].y + 1];
+      const double s = u == 0 ? s0 : s1;
+      const double sc = sxu * ysc[el & 1];
       const double* r = red[el & 1];
       partial[slot] = 4.0 * s * s * sc * sc *
                       ((r[2 * u] + r[2 * u + 1]) + (r[4 + 2 * u] + r[4 + 2 * u + 1]));
@@ -457,6 +532,7 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
       if ((grp == 0) == !(t & 1)) {
         // contraction phase
         const int el = grp == 0 ? (t >> 1) : ((t - 1) >> 1);
+        if (wave == 0 && lane == 0 && el < ne) ysc[el & 1] = Gy[el % NBUF][kTile + 1];
         if (el < ne && entries[e0 + el].slot[unit] >= 0) {
           const uint16_t* Yb = Ys[el % NBUF] + (c0 + li) * xs;
           const double* Gc = Gy[el % NBUF] + c0 + li;
@@ -466,7 +542,6 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
           for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) acc[i][j] = f4{0, 0, 0, 0};
-          // the highest-order products first, the leading ones last
           ch.template contract<3, 3>(acc, xa, Yb, xs);
         }
       } else {
@@ -501,36 +576,62 @@ __global__ __launch_bounds__(512, 1) void pair_split_pp_kernel(
   }
 }
 
-// Kernel instance for the chain lengths of (nterm, pw), one workgroup per
-// CU: xb = 2 runs the ping-pong kernel, xb = 4 the four-unit kernel (both
-// eight waves).
+// Persistent grid: xb = 4 runs the four-unit kernel, one workgroup per CU;
+// xb = 2 runs, for two terms, the two-unit kernel with two workgroups per CU
+// (their barriers independent), for three terms (whose x fragments leave no
+// room for two workgroups) the ping-pong kernel, one workgroup per CU.
+template <bool F16, class Ch>
+static void launch_split_kernel(const fef_plan_s& p, int xb, int ncu, hipStream_t st,
+                                const char* o, int prec, int pw, const double* gap,
+                                const Entry* entries, const WorkItem* items, double* partial,
+                                int32_t* head) {
+  const TileSet& t = p.tiles[prec];
+  const bool two_wg = xb == 2 && Ch::kNterm == 2;
+  const int64_t want = (int64_t)ncu * (two_wg ? 2 : 1);
+  const dim3 grid((unsigned)std::min<int64_t>(want, std::max<int64_t>(t.nitems, 1)));
+  if (xb == 4) {
+    hipLaunchKernelGGL((pair_split_kernel<F16, 4, Ch>), grid, dim3(512), 0, st, p.d_frag,
+                       p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,
+                       head, t.d_grp_off, o, prec, pw, gap, partial);
+  } else if constexpr (Ch::kNterm == 2) {
+    hipLaunchKernelGGL((pair_split_kernel<F16, 2, Ch>), grid, dim3(256), 0, st, p.d_frag,
+                       p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,
+                       head, t.d_grp_off, o, prec, pw, gap, partial);
+  } else {
+    hipLaunchKernelGGL((pair_split_pp_kernel<F16, Ch>), grid, dim3(512), 0, st, p.d_frag,
+                       t.d_xblocks, entries, items, (int32_t)t.nitems, head, t.d_grp_off, o,
+                       prec, pw, gap, partial);
+  }
+}
+
+// Kernel instance for the chain lengths of (nterm, pw).
 template <bool F16, int NTERM>
-static bool launch_split_terms(const fef_plan_s& p, int xb, int pw, dim3 grid, hipStream_t st,
+static bool launch_split_terms(const fef_plan_s& p, int xb, int pw, int ncu, hipStream_t st,
                                const char* o, int prec, const double* gap, const Entry* entries,
                                const WorkItem* items, double* partial, int32_t* head) {
-  const TileSet& t = p.tiles[prec];
-  const int n0 = split_chain(0, pw), n1 = split_chain(1, pw);
-  const int n2 = NTERM == 3 ? split_chain(2, pw) : 0;
-#define FEF_CHAINS(A, B, C)                                                                     \
-  if (n0 == A && n1 == B && n2 == C) {                                                          \
-    if (xb == 4)                                                                                \
-      hipLaunchKernelGGL((pair_split_kernel<F16, 4, NTERM, A, B, C>), grid, dim3(512), 0, st,   \
-                         p.d_frag, p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items,        \
-                         (int32_t)t.nitems, head, t.d_grp_off, o, prec, pw, gap, partial);      \
-    else                                                                                        \
-      hipLaunchKernelGGL((pair_split_pp_kernel<F16, NTERM, A, B, C>), grid, dim3(512), 0, st,   \
-                         p.d_frag, t.d_xblocks, entries, items, (int32_t)t.nitems, head,        \
-                         t.d_grp_off, o, prec, pw, gap, partial);                               \
-    return true;                                                                                \
-  }
   if constexpr (NTERM == 2) {
-    FEF_CHAINS(1, 1, 0) FEF_CHAINS(1, 2, 0) FEF_CHAINS(2, 3, 0) FEF_CHAINS(2, 4, 0)
-    FEF_CHAINS(3, 5, 0)
+    const int nc = (3 * pw + 31) / 32;
+#define FEF_CHAIN(NC)                                                                          \
+  if (nc == NC) {                                                                              \
+    launch_split_kernel<F16, SplitChain2<F16, NC>>(p, xb, ncu, st, o, prec, pw, gap, entries,  \
+                                                   items, partial, head);                      \
+    return true;                                                                               \
+  }
+    FEF_CHAIN(1) FEF_CHAIN(2) FEF_CHAIN(3) FEF_CHAIN(4) FEF_CHAIN(5) FEF_CHAIN(6) FEF_CHAIN(7)
+    FEF_CHAIN(8)
+#undef FEF_CHAIN
   } else {
+    const int n0 = split_chain(0, pw), n1 = split_chain(1, pw), n2 = split_chain(2, pw);
+#define FEF_CHAINS(A, B, C)                                                                    \
+  if (n0 == A && n1 == B && n2 == C) {                                                         \
+    launch_split_kernel<F16, SplitChains<F16, 3, A, B, C>>(p, xb, ncu, st, o, prec, pw, gap,   \
+                                                           entries, items, partial, head);     \
+    return true;                                                                               \
+  }
     FEF_CHAINS(1, 1, 1) FEF_CHAINS(1, 1, 2) FEF_CHAINS(1, 2, 3) FEF_CHAINS(2, 3, 4)
     FEF_CHAINS(2, 3, 5) FEF_CHAINS(2, 4, 6) FEF_CHAINS(3, 5, 7) FEF_CHAINS(3, 5, 8)
-  }
 #undef FEF_CHAINS
+  }
   return false;
 }
 
@@ -542,16 +643,15 @@ hipError_t launch_split_pairs(const fef_plan_s& p, const void* ops, const double
   const int xb = p.tiles[prec].xb;
   if (pw > 80 || pw < 8 || pw % 8 != 0) return hipErrorInvalidValue;
   if ((p.ops_header & 15) != 0) return hipErrorInvalidValue;  // 16-byte copies
-  const dim3 g((unsigned)std::min<int64_t>(ncu, std::max<int64_t>(p.tiles[prec].nitems, 1)));
   bool ok = false;
   if (prec == FEF_FP16X2)
-    ok = launch_split_terms<true, 2>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+    ok = launch_split_terms<true, 2>(p, xb, pw, ncu, st, o, (int)prec, gap, entries, items,
                                      partial, head);
   else if (prec == FEF_BF16X2)
-    ok = launch_split_terms<false, 2>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+    ok = launch_split_terms<false, 2>(p, xb, pw, ncu, st, o, (int)prec, gap, entries, items,
                                       partial, head);
   else if (prec == FEF_BF16X3)
-    ok = launch_split_terms<false, 3>(p, xb, pw, g, st, o, (int)prec, gap, entries, items,
+    ok = launch_split_terms<false, 3>(p, xb, pw, ncu, st, o, (int)prec, gap, entries, items,
                                       partial, head);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();

@@ -17,11 +17,12 @@ def test_pair_flop_counts_config0():
     s = fefgen.make_system(0)
     # 28 water pairs, 2 ov_x ov_y P0 each
     assert bench.pair_flops(s) == 28 * 2 * 95 * 95 * 72
-    # issued: whole 96-row tiles; FP64 K = 72; split: the leading product
-    # over K = 72 rounded to 96 and the two cross products over 144 rounded
-    # to 160
+    # issued: whole 96-row tiles; FP64 K = 72; two terms: the three
+    # products over K = 3 * 72 rounded to 224; three terms: the chains of
+    # orders 0, 1, 2 over 72, 144, 216 rounded to 96, 160, 224
     assert bench.pair_issued_flops(s, "f64") == 28 * 2 * 96 * 96 * 72
-    assert bench.pair_issued_flops(s, "fp16x2") == 28 * 2 * 96 * 96 * (96 + 160)
+    assert bench.pair_issued_flops(s, "fp16x2") == 28 * 2 * 96 * 96 * 224
+    assert bench.pair_issued_flops(s, "bf16x3") == 28 * 2 * 96 * 96 * (96 + 160 + 224)
     assert bench.pair_issued_flops(s, "bf16x2") / bench.pair_flops(s) > 3.0
 
 
@@ -44,3 +45,16 @@ def test_traffic_record_matches_sources():
     else:
         assert got is None
     assert bench.traffic_from_profiles("fp16x2", "no-such-workload") is None
+
+
+def test_scf_stage_model_config0():
+    """Work model of the SCF stage rooflines on 8 water fragments (nbf 24,
+    nocc 5, P 72): packed triangle 300 entries per slice."""
+    s = fefgen.make_system(0)
+    m = bench.scf_stage_model(s)
+    tri = 24 * 25 // 2
+    assert m["moments_bytes"] == 8 * (8 * 72 * tri + 8 * tri + 8 * 72)
+    nn = 8 * 8 * 24 * 24
+    assert m["field_bytes"] == 8 * 8 * 72 * tri + 8 * 8 * 72 + 8 * s.G.size + 2 * nn + (
+        nn if s.htilde is not None else 0)
+    assert m["eigh_flops"] == 8 * (9.0 * 24 ** 3 + 2.0 * 24 * 24 * 5)
