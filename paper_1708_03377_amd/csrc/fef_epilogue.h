@@ -76,6 +76,24 @@ __device__ inline double weighted_tiles_f32_regs(const f4 (&acc)[TI][TJ], const 
   return (double)sum;
 }
 
+// One tile of weighted_tiles_f32_regs: the same operations on one tile, its
+// FP32 quotient returned (summing these in the order (i, j) from 0 gives
+// the FP32 sum weighted_tiles_f32_regs forms).
+__device__ inline float weighted_tile_f32(const f4& acc, const float (&dx)[4], float dy) {
+  const float d0 = dx[0] + dy, d1 = dx[1] + dy;
+  const float d2 = dx[2] + dy, d3 = dx[3] + dy;
+  const float v0 = acc[0], v1 = acc[1];
+  const float v2 = acc[2], v3 = acc[3];
+  const float n01 = fmaf(v0 * v0, d1, (v1 * v1) * d0);
+  const float n23 = fmaf(v2 * v2, d3, (v3 * v3) * d2);
+  const float a = d0 * d1, b = d2 * d3;
+  const float num = fmaf(b, n01, a * n23);
+  const float den = a * b;
+  const float r = __builtin_amdgcn_rcpf(den);
+  const float q = num * r;
+  return fmaf(r, fmaf(-den, q, num), q);
+}
+
 // The same with the row gaps gx and column gaps gy read from memory (gy in
 // FP32 or FP64, converted on load).
 template <int TI, int TJ, typename GyT>

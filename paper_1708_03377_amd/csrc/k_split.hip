@@ -416,6 +416,201 @@ __global__ __launch_bounds__(128 * XB, XB == 2 ? 2 : 1) void pair_split_kernel(
 }
 
 
+// Pipelined two-term split kernel for the common plane width (pw fixed at
+// compile time): two x units per workgroup, two waves each, two workgroups
+// per CU, as the two-unit kernel.  Each wave splits the 96 y columns of an
+// entry into two halves of 48 and issues the MFMA chain of one half while
+// it weights the accumulators of the half before on the VALU, so that the
+// matrix core and the VALU of one wave work side by side:
+//   stage A(e): contract half 0 of entry e   | weight half 1 of entry e - 1
+//   stage B(e): contract half 1 of entry e   | weight half 0 of entry e
+// A stage runs chunk by chunk (the chunk's three B fragments and nine
+// MFMAs, then one or two of the nine tiles to weight), each chunk fenced
+// from the next so that the scheduler keeps the interleave and only one
+// chunk's temporaries are live.  One workgroup barrier per entry (after
+// stage B), y tiles in two LDS buffers with the next entry's copy issued at
+// the start of an entry; a wave whose unit has no pair with an entry skips
+// that entry's chains and weighting.  The sums are those of the two-unit
+// kernel in the same order (tiles (i, j) of a half in FP32, the two halves
+// in FP64, the unit's two waves), and the entry's partial slot is written
+// after the next barrier.
+template <bool kFp16, int NC, int PW>
+__global__ __launch_bounds__(256, 2) void pair_split_pipe_kernel(
+    const FragInfo* __restrict__ frag, const XBlock* __restrict__ xblocks,
+    const Entry* __restrict__ entries, const WorkItem* __restrict__ items, int32_t nitems,
+    int32_t* __restrict__ head, const int32_t* __restrict__ grp_off, const char* __restrict__ ops,
+    int prec, const double* __restrict__ gap, double* __restrict__ partial) {
+  constexpr int XB = 2, NT = 256, NW = 4;
+  constexpr int TI = 3, TJ = 3;
+  constexpr int XS = 2 * PW + 8;             // row stride (16-bit elements)
+  constexpr int TILE_CH = kTile * XS / 8;     // 16-byte chunks per tile
+  constexpr int GL = kTile + 2;               // gaps, then the y operand's scales
+  __shared__ __align__(16) uint16_t Ys0[kTile * XS];
+  __shared__ __align__(16) uint16_t Ys1[kTile * XS];
+  __shared__ __align__(16) double Gy0[GL];
+  __shared__ __align__(16) double Gy1[GL];
+  __shared__ float Gx[XB * kTile];
+  __shared__ double red[2][NW];
+  __shared__ int32_t s_item;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int unit = wave >> 1, sub = wave & 1;
+  const int r0 = sub * 48;
+  const double* hdr = reinterpret_cast<const double*>(ops);
+  const u16x8 zero = {0, 0, 0, 0, 0, 0, 0, 0};
+  const SplitChain2<kFp16, NC> ch(PW, lk);
+  auto issue = [&](int E, uint16_t* Y, double* G) __attribute__((always_inline)) {
+    const char* src = ops + entries[E].off_R;
+    for (int g = wave; g * 64 < TILE_CH; g += NW) {
+      const int c = g * 64 + lane;
+      if (c < TILE_CH)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 16 * (int64_t)c),
+                                         (lds_void_t*)(Y + g * 512), 16, 0, 0);
+    }
+    if (wave == NW - 1 && lane <= kTile / 2) {
+      const double* gsrc = lane < kTile / 2 ? gap + entries[E].off_gap + 2 * lane
+                                            : hdr + 2 * entries[E].y;
+      __builtin_amdgcn_global_load_lds(static_cast<const void*>(gsrc), (lds_void_t*)(G), 16, 0, 0);
+    }
+  };
+  using yes = std::true_type;
+  using no = std::false_type;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = pull_item(head, grp_off, blockIdx.x & 7);
+    __syncthreads();
+    const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it < 0 || it >= nitems) break;
+    const int32_t xbid = items[it].xblock, e0 = items[it].e0, ne = items[it].ne;
+    if (ne == 0) continue;  // an item emptied by a pair mask
+    issue(e0, Ys0, Gy0);
+    const int fxi = xblocks[xbid].f[unit];
+    const int mt = xblocks[xbid].mt[unit];
+    const double sx = fxi >= 0 ? hdr[2 * fxi] : 0.0;
+    u16x8 xa[TI][NC];
+    if (fxi >= 0) {
+      ch.template load_x<TI>(xa, reinterpret_cast<const uint16_t*>(ops + frag[fxi].off_L[prec]) +
+                            (int64_t)(mt * kTile + r0 + li) * XS, XS);
+    } else {
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xa[i][c] = zero;
+    }
+    for (int t = threadIdx.x; t < XB * kTile; t += NT) {
+      const int u = t / kTile, m = t - (t / kTile) * kTile;
+      const int f = xblocks[xbid].f[u];
+      Gx[t] = f >= 0 ? (float)gap[frag[f].off_gap + xblocks[xbid].mt[u] * kTile + m] : -1.0f;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    float dx[TI][4];
+    {
+      const float* gx = Gx + unit * kTile + r0 + 4 * lk;
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dx[i][r] = gx[16 * i + r];
+    }
+    f4 acc0[TI][TJ], acc1[TI][TJ];
+    float dy0[TJ], dy1[TJ];
+    // one stage on LDS buffer (Y, G): the chain of half h into acc (and its
+    // column gaps into dy) if C, the weighting of accw with gaps dyw if Wt
+    auto stage = [&](auto C, auto Wt, const uint16_t* Y, const double* G, int h,
+                     f4(&acc)[TI][TJ], float(&dy)[TJ], const f4(&accw)[TI][TJ],
+                     const float(&dyw)[TJ]) __attribute__((always_inline)) -> double {
+      constexpr bool kC = decltype(C)::value, kW = decltype(Wt)::value;
+      constexpr int NG = kC ? NC : 1;
+      const uint16_t* Yb = Y + (48 * h + li) * XS;
+      if constexpr (kC) {
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) dy[j] = (float)G[48 * h + li + 16 * j];
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+          for (int j = 0; j < TJ; ++j) acc[i][j] = f4{0, 0, 0, 0};
+      }
+      float w = 0.0f;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if constexpr (kC) {
+          u16x8 b[TJ];
+#pragma unroll
+          for (int j = 0; j < TJ; ++j)
+            b[j] = *reinterpret_cast<const u16x8*>(Yb + 16 * j * XS + ch.yoff[g]);
+#pragma unroll
+          for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = mma16<kFp16>(xa[i][g], b[j], acc[i][j]);
+        }
+        if constexpr (kW) {
+          // the nine tiles over NG groups, the first 9 % NG groups one more
+          constexpr int q = 9 / NG, rm = 9 % NG;
+          const int t0 = g * q + (g < rm ? g : rm), nt = q + (g < rm ? 1 : 0);
+#pragma unroll
+          for (int tt = 0; tt < q + (rm ? 1 : 0); ++tt)
+            if (tt < nt) {
+              const int t = t0 + tt, ti = t / TJ, tj = t - TJ * (t / TJ);
+              w += weighted_tile_f32(accw[ti][tj], dx[ti], dyw[tj]);
+            }
+          // the group's weighting happens here, not sunk past later chunks
+          if constexpr (kC) asm volatile("" : "+v"(w));
+        }
+        if constexpr (kC && kW) __builtin_amdgcn_sched_barrier(0);
+      }
+      return (double)w;
+    };
+    auto run = [&](bool c, bool w, const uint16_t* Y, const double* G, int h, f4(&acc)[TI][TJ],
+                   float(&dy)[TJ], const f4(&accw)[TI][TJ], const float(&dyw)[TJ])
+                   __attribute__((always_inline)) -> double {
+      if (c && w) return stage(yes{}, yes{}, Y, G, h, acc, dy, accw, dyw);
+      if (c) return stage(yes{}, no{}, Y, G, h, acc, dy, accw, dyw);
+      if (w) return stage(no{}, yes{}, Y, G, h, acc, dy, accw, dyw);
+      return 0.0;
+    };
+    // entry el on buffer (Y, G), the next entry's buffer (Yn, Gn)
+    bool vprev = false;   // the previous entry had a pair for this wave's unit
+    int slot_prev = -1;
+    double sc_prev = 0.0, s_prev = 0.0;
+    bool v0 = entries[e0].slot[unit] >= 0;
+    (void)run(v0, false, Ys0, Gy0, 0, acc0, dy0, acc1, dy1);
+    auto entry = [&](int el, const uint16_t* Y, const double* G, uint16_t* Yn, double* Gn)
+                     __attribute__((always_inline)) {
+      const int e = e0 + el;
+      const int slot = entries[e].slot[unit];
+      const bool v = slot >= 0;
+      if (el + 1 < ne) issue(e + 1, Yn, Gn);
+      const double sy = G[kTile + 1];
+      // B(el): half 1 of el | weight half 0 of el
+      double part = run(v, v, Y, G, 1, acc1, dy1, acc0, dy0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      // entry el - 1's partial slot: its wave sums are in red[(el - 1) & 1]
+      if (el >= 1 && sub == 0 && lane == 0 && slot_prev >= 0)
+        partial[slot_prev] = 4.0 * s_prev * s_prev * sc_prev * sc_prev *
+                             (red[(el - 1) & 1][wave] + red[(el - 1) & 1][wave + 1]);
+      // A(el + 1): half 0 of el + 1 | weight half 1 of el
+      const bool vn = el + 1 < ne && entries[e + 1].slot[unit] >= 0;
+      part += run(vn, v, Yn, Gn, 0, acc0, dy0, acc1, dy1);
+      const double mine = v ? wave_sum_dpp(part) : 0.0;
+      if (lane == 0) red[el & 1][wave] = mine;
+      slot_prev = slot;
+      s_prev = v ? entries[e].s[unit] : 0.0;
+      sc_prev = sx * sy;
+    };
+    for (int el = 0; el < ne; el += 2) {
+      entry(el, Ys0, Gy0, Ys1, Gy1);
+      if (el + 1 < ne) entry(el + 1, Ys1, Gy1, Ys0, Gy0);
+    }
+    __syncthreads();
+    if (sub == 0 && lane == 0 && slot_prev >= 0)
+      partial[slot_prev] = 4.0 * s_prev * s_prev * sc_prev * sc_prev *
+                           (red[(ne - 1) & 1][wave] + red[(ne - 1) & 1][wave + 1]);
+    (void)vprev;
+  }
+}
+
+
 // Ping-pong split pair kernel: two x units per workgroup, eight waves, one
 // workgroup per CU.  Waves w and w + 4 share a SIMD and hold the same 48 x
 // rows of one unit (wave w: columns 0-47 of the streamed y tile, wave w + 4:
@@ -594,6 +789,14 @@ static void launch_split_kernel(const fef_plan_s& p, int xb, int ncu, hipStream_
                        p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,
                        head, t.d_grp_off, o, prec, pw, gap, partial);
   } else if constexpr (Ch::kNterm == 2) {
+    if constexpr (Ch::NX == 7) {
+      if (pw == 72) {
+        hipLaunchKernelGGL((pair_split_pipe_kernel<F16, 7, 72>), grid, dim3(256), 0, st,
+                           p.d_frag, t.d_xblocks, entries, items, (int32_t)t.nitems, head,
+                           t.d_grp_off, o, prec, gap, partial);
+        return;
+      }
+    }
     hipLaunchKernelGGL((pair_split_kernel<F16, 2, Ch>), grid, dim3(256), 0, st, p.d_frag,
                        p.d_pair, p.d_slot_pair, t.d_xblocks, entries, items, (int32_t)t.nitems,
                        head, t.d_grp_off, o, prec, pw, gap, partial);

@@ -218,6 +218,27 @@ def test_tilings_agree(torch, prec, tiles):
             np.testing.assert_allclose(got, base, rtol=1e-12 if prec == "f64" else 1e-6, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["bf16x2", "fp16x2"])
+def test_split_kernels_bitwise_on_water_width(torch, prec):
+    """Water fragments (P = 72): the pipelined two-unit kernel (xb = 2) and
+    the four-unit kernel (xb = 4) give bitwise the same pair energies (same
+    products, same tile and half sums in the same order), and both match
+    the oracle."""
+    import paper_1708_03377_amd as lib
+    sysm = fefgen.make_system(0)
+    ref, _ = ofef.pair_energies(sysm)
+    ctx = ctx_for(sysm)
+    ctx.half_transform(PREC[prec])
+    out = {}
+    for xb, yc in ((2, 1), (2, 16), (4, 3), (4, 16)):
+        lib.fef_plan_set_tiles(ctx.plan, PREC[prec], xb, yc)
+        out[(xb, yc)] = ctx.pair_energies(PREC[prec])[0].cpu().numpy().copy()
+    base = out[(4, 16)]
+    assert np.max(np.abs(base - ref)) <= 1e-6
+    for k, v in out.items():
+        assert np.array_equal(v, base), k
+
+
 def test_graph_replays_match_eager(torch):
     """A captured FEF pass replays bitwise like the eager calls, also with
     eager work and synchronisations between replays.  The packed coefficient
