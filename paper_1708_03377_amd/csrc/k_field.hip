@@ -367,25 +367,41 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
           if (q < nq && 2 * lane + 128 * c < nt)
             *reinterpret_cast<double2*>(bo + (int64_t)q * nt + 2 * lane + 128 * c) = bv[q][c];
   } else {
-    for (int k = lane; k < nt; k += 64) {
-      const double dk = d[k];
-      int s = 0;
-      if (kPack) {
-        int mu, nu;
-        tri_row_col(k, n, mu, nu);
-        s = mu * n + nu;
+    // large or odd triangles: kMomU positions per lane at a time, all of
+    // their loads in flight before the products (rows past nq re-read row
+    // nq - 1 and positions past nt are clamped, their density weight 0; the
+    // products are added in the same k order as one position at a time)
+    constexpr int kMomU = 4;
+    for (int k0 = lane; k0 < nt; k0 += 64 * kMomU) {
+      double dk[kMomU], v[kMomQW][kMomU];
+      int kc[kMomU];
+#pragma unroll
+      for (int u = 0; u < kMomU; ++u) {
+        const int k = k0 + 64 * u;
+        kc[u] = min(k, nt - 1);
+        dk[u] = k < nt ? d[kc[u]] : 0.0;
       }
 #pragma unroll
-      for (int q = 0; q < kMomQW; ++q)
-        if (q < nq) {
-          double v;
-          if (kPack) {
-            v = bf[(int64_t)q * nn + s];
-            bo[(int64_t)q * nt + k] = v;
-          } else {
-            v = b[(int64_t)q * nt + k];
-          }
-          acc[q] = fma(v, dk, acc[q]);
+      for (int u = 0; u < kMomU; ++u) {
+        int s = 0;
+        if (kPack) {
+          int mu, nu;
+          tri_row_col(kc[u], n, mu, nu);
+          s = mu * n + nu;
+        }
+#pragma unroll
+        for (int q = 0; q < kMomQW; ++q) {
+          const int64_t row = min(q, nq - 1);
+          v[q][u] = kPack ? bf[row * nn + s] : b[row * nt + kc[u]];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // every load ahead of the arithmetic
+#pragma unroll
+      for (int u = 0; u < kMomU; ++u)
+#pragma unroll
+        for (int q = 0; q < kMomQW; ++q) {
+          if (k0 + 64 * u < nt) acc[q] = fma(v[q][u], dk[u], acc[q]);
+          if (kPack && q < nq && k0 + 64 * u < nt) bo[(int64_t)q * nt + k0 + 64 * u] = v[q][u];
         }
     }
   }
@@ -397,30 +413,39 @@ __global__ __launch_bounds__(256) void moments_packed_kernel(const FragInfo* __r
 }
 
 // out = F0 + h~ + 2 sum_P B[P] phi_P from the packed slices, both mirror
-// elements written.
-__global__ __launch_bounds__(1024) void jbuild_packed_kernel(const FragInfo* __restrict__ frag,
-                                                            const int64_t* __restrict__ off_Bp,
-                                                            const double* __restrict__ Bp,
-                                                            const double* __restrict__ phi,
-                                                            const double* __restrict__ F0,
-                                                            const double* __restrict__ htilde,
-                                                            double* __restrict__ out) {
+// elements written.  A workgroup takes 64 triangle positions; its four
+// waves take the slices P = g mod 4 (four partial sums each, so that loads
+// of several slices are in flight), and the four wave sums meet in LDS in a
+// fixed order.  Large fragments (the nucleobase's triangle of 11,325
+// positions over 450 slices) so spread over many workgroups.
+constexpr int kJbK = 64;
+__global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __restrict__ frag,
+                                                           const int64_t* __restrict__ off_Bp,
+                                                           const double* __restrict__ Bp,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ F0,
+                                                           const double* __restrict__ htilde,
+                                                           double* __restrict__ out) {
+  __shared__ double part[4][kJbK];
   const FragInfo fi = frag[blockIdx.x];
   const int n = fi.nbf, nt = n * (n + 1) / 2;
-  const int k = blockIdx.y * blockDim.x + threadIdx.x;
-  if (k >= nt) return;
-  const double* b = Bp + off_Bp[blockIdx.x] + k;
+  if ((int)blockIdx.y * kJbK >= nt) return;  // uniform over the workgroup
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int k = blockIdx.y * kJbK + lane;
+  const int kc = min(k, nt - 1);  // every load in bounds; the sum of k >= nt is not stored
+  const double* b = Bp + off_Bp[blockIdx.x] + kc;
   const double* ph = phi + fi.off_aux;
-  // four independent partial sums (P mod 4), so that loads of several
-  // slices are in flight at once
   double a4[4] = {0.0, 0.0, 0.0, 0.0};
-  int P = 0;
-#pragma unroll 4
-  for (; P + 4 <= fi.naux; P += 4)
+  int P = g;
+#pragma unroll 2
+  for (; P + 12 < fi.naux; P += 16)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a4[u] = fma(b[(int64_t)(P + u) * nt], ph[P + u], a4[u]);
-  for (; P < fi.naux; ++P) a4[0] = fma(b[(int64_t)P * nt], ph[P], a4[0]);
-  const double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    for (int u = 0; u < 4; ++u) a4[u] = fma(b[(int64_t)(P + 4 * u) * nt], ph[P + 4 * u], a4[u]);
+  for (; P < fi.naux; P += 4) a4[0] = fma(b[(int64_t)P * nt], ph[P], a4[0]);
+  part[g][lane] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  __syncthreads();
+  if (g != 0 || k >= nt) return;
+  const double acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
   int mu, nu;
   tri_row_col(k, n, mu, nu);
   const double j2 = 2.0 * acc;
@@ -691,10 +716,8 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
                      p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                      p.d_naux_cls_off, ws_d, ws_phi);
-  // one block per fragment triangle when it fits 1024 threads (water: 320)
-  const int jt = std::min(1024, (ntmax + 63) / 64 * 64);
-  hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + jt - 1) / jt), dim3(jt), 0, st,
-                     p.d_frag, p.d_off_Bp, Bp, ws_phi, F0, htilde, out);
+  hipLaunchKernelGGL(jbuild_packed_kernel, dim3(p.nfrag, (ntmax + kJbK - 1) / kJbK), dim3(256), 0,
+                     st, p.d_frag, p.d_off_Bp, Bp, ws_phi, F0, htilde, out);
   return hipGetLastError();
 }
 
