@@ -44,7 +44,8 @@
  *   status synchronously and enqueue nothing; a failed launch returns
  *   FEF_E_HIP.  Data-dependent conditions are reported in the device word
  *   `flags` (read it after synchronising): bit 0 = some fragment has a
- *   non-positive HOMO-LUMO gap, bit 1 = a non-finite pair energy.  The
+ *   non-positive HOMO-LUMO gap, bit 1 = a non-finite pair energy, bit 2 =
+ *   a coupled pair solve stopped at its iteration limit.  The
  *   library never clears `flags`; the caller zeroes it.
  *   No C++ exception crosses this interface.
  */
@@ -69,6 +70,7 @@ typedef int32_t fef_status;
 
 #define FEF_FLAG_GAP 1
 #define FEF_FLAG_NONFINITE 2
+#define FEF_FLAG_NOCONV 4
 
 /* Arithmetic of the pair contraction (a reduced-precision mode rounds the
  * half-transformed operands; every other step stays FP64). */
@@ -125,7 +127,8 @@ typedef enum {
   FEF_Q_MASKED_WS_BYTES = 15, /* workspace of fef_pair_energies_masked   */
   FEF_Q_SURR_WS_BYTES = 16, /* workspace of fef_coupling_modes and
                                fef_fragment_invariants                  */
-  FEF_Q_BPACK_ELEMS = 17    /* doubles in the packed coefficient pool    */
+  FEF_Q_BPACK_ELEMS = 17,   /* doubles in the packed coefficient pool    */
+  FEF_Q_COUPLED_WS_BYTES = 18 /* workspace of fef_coupled_pair_energies  */
 } fef_query;
 
 /* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES,
@@ -310,6 +313,38 @@ fef_status fef_pair_energies_masked(fef_plan plan, const void* ops, const double
 fef_status fef_pair_energies_noalloc(fef_plan plan, const void* ops, const double* eps,
                                      fef_prec prec, double* E2_pair, double* E2_total,
                                      int32_t* flags, void* stream);
+
+/* Pair energies with the dimer doubles coupled through the two-body part of
+ * the zeroth-order Hamiltonian (Sec. II.B: Eq. partitioning0 keeps W^[0] in
+ * H0, and Eq. dimDoubles becomes, for every pair, the linear system
+ *     (D + W) t = -v,   E2_xy = 4 sum_{ia,jb} v[ia,jb] t[ia,jb],
+ * v = (ia|jb), D = eps_a + eps_b - eps_i - eps_j, in place of t = -v / D).
+ * Readings: W is the inter-fragment Coulomb operator of the factored
+ * integrals (the only two-body operator the integral model defines), in
+ * normal order, acting on the dimer doubles:
+ *     (W t)[i,a,j,b] = + (aa'|bb') t[i,a',j,b'] - (aa'|j'j) t[i,a',j',b]
+ *                      - (i'i|bb') t[i',a,j,b'] + (i'i|j'j) t[i',a,j',b]
+ * (sums over primed indices, (pq|rs) = (pq|rs)^{xy} of the integral model
+ * with MO coefficients C); F^[0] is the diagonal of the canonical orbital
+ * energies.  Each pair is solved by conjugate gradients preconditioned with
+ * D, from t = -v / D, stopped when ||r|| <= tol ||v|| (FP64 throughout).
+ *   B, C, eps, G : input pools (device), as for fef_half_transform and
+ *                  fef_pair_energies.
+ *   tol, maxit   : stopping rule (tol >= 0 finite, maxit >= 0; maxit = 0
+ *                  gives the uncoupled energy of fef_pair_energies).
+ *   E2_pair      : [npair] out, in the caller's pair order (device).
+ *   E2_total     : [1] out, FP64 sum over pairs in a fixed order (device).
+ *   iters        : optional [npair] int32 out, CG iterations per pair.
+ *   flags        : bit 1 for a non-finite energy, bit 2 when a pair stopped
+ *                  at maxit without meeting tol.
+ *   ws           : FEF_Q_COUPLED_WS_BYTES bytes (device).
+ * Results are bitwise reproducible for a given plan.  A plan whose pairs
+ * need more LDS than a workgroup has returns FEF_E_UNSUPPORTED. */
+fef_status fef_coupled_pair_energies(fef_plan plan, const double* B, const double* C,
+                                     const double* eps, const double* G, double tol,
+                                     int32_t maxit, double* E2_pair, double* E2_total,
+                                     int32_t* iters, int32_t* flags, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /* ------------------------------------------------------------------------
  * Distant-pair surrogate.  A project addition: the paper has no learned

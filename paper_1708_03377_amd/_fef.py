@@ -24,12 +24,14 @@ FEF_E_HIP = -5
 FEF_E_UNSUPPORTED = -6
 FEF_FLAG_GAP = 1
 FEF_FLAG_NONFINITE = 2
+FEF_FLAG_NOCONV = 4
 
 PREC = {"f64": 0, "f32": 1, "bf16x2": 2, "fp16x2": 3, "bf16x3": 4}
 
 Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES = range(5)
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
 Q_NSLOT, Q_NENTRIES, Q_MASKED_WS_BYTES, Q_SURR_WS_BYTES, Q_BPACK_ELEMS = 13, 14, 15, 16, 17
+Q_COUPLED_WS_BYTES = 18
 
 MLP_NIN, MLP_NHID, MLP_NPARAM, MLP_STRIDE, MLP_NSTATS = 17, 128, 18945, 18952, 36
 
@@ -43,7 +45,7 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
                 "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_plan_stage_timing",
-                "fef_plan_stage_ms", "fef_status_string")
+                "fef_plan_stage_ms", "fef_coupled_pair_energies", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -111,6 +113,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_pack_coefficients.argtypes = [vp, vp, vp, vp]
     lib.fef_scf_step_packed.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.fef_pair_energies_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.fef_coupled_pair_energies.argtypes = [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp,
+                                              sz, vp]
     lib.fef_plan_stage_timing.argtypes = [vp, i32]
     lib.fef_plan_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fef_status_string.argtypes = [i32]
@@ -234,6 +238,13 @@ def fef_pair_energies_noalloc(plan, ops, eps, prec, E2_pair, E2_total, flags, st
     _check("fef_pair_energies_noalloc", load_library().fef_pair_energies_noalloc(
         plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(E2_pair), _ptr(E2_total), _ptr(flags),
         _stream(stream)))
+
+
+def fef_coupled_pair_energies(plan, B, C, eps, G, tol, maxit, E2_pair, E2_total, iters, flags,
+                              ws, stream=None):
+    _check("fef_coupled_pair_energies", load_library().fef_coupled_pair_energies(
+        plan.handle, _ptr(B), _ptr(C), _ptr(eps), _ptr(G), float(tol), int(maxit), _ptr(E2_pair),
+        _ptr(E2_total), _ptr(iters), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
 def fef_coulomb_field(plan, B, G, D, J, ws, stream=None):

@@ -130,6 +130,22 @@ struct Chunk {
   int32_t frag, pad;
 };
 
+namespace fef {
+// Coupled dimer doubles: offsets (doubles) inside one pair slot of a group.
+struct CgSlot {
+  int64_t v, d, t, r, p, ap, q, ph, hp, hh, size;
+  int64_t nmax;  // largest amplitude count ov_x ov_y of the group
+};
+// Pairs of one class of x (a list range), solved by nslots workgroups; lds:
+// the search direction and its product live in LDS.
+struct CoupledGroup {
+  int32_t first = 0, count = 0, nslots = 0;
+  bool lds = false;
+  size_t lds_bytes = 0;
+  CgSlot L{};
+};
+}  // namespace fef
+
 // Stage markers of an SCF step: start, after the density, after the
 // moments, after the field and Coulomb build, after the eigensolver.
 constexpr int kStageMarks = 5;
@@ -196,6 +212,10 @@ struct fef_plan_s {
   // G_{0,0} posed as one "fragment" for the eigensolver (coupling modes)
   fef::FragInfo* d_gfrag = nullptr;
   int32_t* d_glist = nullptr;
+  // coupled dimer doubles: pair groups and their pair lists
+  std::vector<fef::CoupledGroup> cp_groups;
+  std::vector<int32_t> cp_list;
+  int32_t* d_cp_list = nullptr;
 };
 
 namespace fef {
@@ -297,6 +317,9 @@ inline void stage_mark(const fef_plan_s& p, int i, hipStream_t st) {
 
 // Compute units of the current device (queried once, cached).
 int compute_units();
+// coupled dimer doubles: pair groups (plan creation) and workspace bytes
+void coupled_setup(fef_plan_s& p);
+int64_t coupled_ws_bytes(const fef_plan_s& p);
 
 // One-time kernel attributes (dynamic LDS above 64 KB).
 

@@ -129,6 +129,22 @@ class Context:
         self.half_transform(prec)
         return self.pair_energies(prec)
 
+    def coupled_pair_energies(self, tol: float = 1e-14, maxit: int = 500):
+        """Pair energies with the W^[0]-coupled dimer doubles on the current
+        orbitals; returns (E2_pair, E2_total, iterations per pair).  Its
+        workspace is allocated on first use."""
+        torch = self.torch
+        if getattr(self, "_cp_ws", None) is None:
+            self._cp_ws = torch.empty(max(self._q(F.Q_COUPLED_WS_BYTES), 1), dtype=torch.uint8,
+                                      device=self.device)
+            self._cp_E = torch.zeros(max(self.npair, 1), dtype=torch.float64, device=self.device)
+            self._cp_tot = torch.zeros(1, dtype=torch.float64, device=self.device)
+            self._cp_it = torch.zeros(max(self.npair, 1), dtype=torch.int32, device=self.device)
+        F.fef_coupled_pair_energies(self.plan, self.B, self.C, self.eps, self.G, tol, maxit,
+                                    self._cp_E, self._cp_tot, self._cp_it, self.flags,
+                                    self._cp_ws, self.stream())
+        return self._cp_E[:self.npair], self._cp_tot, self._cp_it[:self.npair]
+
     # ---- surrogate ---------------------------------------------------------
     def pair_energies_masked(self, prec: int, select):
         """Exact pair energies of the selected pairs; the others keep the

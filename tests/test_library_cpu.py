@@ -56,6 +56,16 @@ def test_null_arguments_rejected():
     assert lib.fef_coulomb_field(None, None, None, None, None, None, 0, None) == F.FEF_E_ARG
     assert lib.fef_scf_step(None, None, None, None, None, None, None, None, None, None, None,
                             0, None) == F.FEF_E_ARG
+    assert lib.fef_coupled_pair_energies(None, None, None, None, None, 1e-14, 10, None, None,
+                                         None, None, None, 0, None) == F.FEF_E_ARG
+
+
+def test_coupled_flag_and_query_constants_match_header():
+    import re
+    F, lib = _lib()
+    txt = open(os.path.join(ROOT, "include", "fef.h")).read()
+    assert re.search(rf"#define FEF_FLAG_NOCONV {F.FEF_FLAG_NOCONV}\b", txt)
+    assert re.search(rf"FEF_Q_COUPLED_WS_BYTES = {F.Q_COUPLED_WS_BYTES}\b", txt)
 
 
 def test_bad_shapes_rejected_before_device():
