@@ -60,19 +60,49 @@ constexpr int64_t kCgSlotBudget = (int64_t)8 << 30;
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+// Two block-wide sums at once (fixed order: lanes, then waves); both results
+// in every thread.
+__device__ __attribute__((always_inline)) inline void block_sum_pair(double& a, double& b,
+                                                                     double (*red2)[kCgWaves]) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red2[0][w] = a;
+    red2[1][w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int k = 0; k < kCgWaves; ++k) {
+    sa += red2[0][k];
+    sb += red2[1][k];
+  }
+  __syncthreads();
+  a = sa;
+  b = sb;
+}
+
 __device__ __attribute__((always_inline)) inline d4v mma64(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // Offset of element (m, k) of an operator block stored in MFMA A-operand
 // tiles: tile (m / 16, k / 4) holds 64 consecutive doubles, lane l = 16 (k %
-// 4) + m % 16 reading element l (the FP64 16x16x4 A-operand layout); KS =
-// ceil(M / 4) tiles per row of tiles.
+// 4) + m % 16 reading element l (the FP64 16x16x4 A-operand layout).  A row
+// of tiles holds tile_ks(M) tiles, ceil(M / 4) rounded up to a multiple of
+// kApplyKC (the products load whole chunks of kApplyKC tiles; the padding
+// is zero).
+constexpr int kApplyKC = 8;
+__host__ __device__ inline int tile_ks(int64_t M) {
+  return (int)((((M + 3) / 4) + kApplyKC - 1) / kApplyKC * kApplyKC);
+}
 __device__ __attribute__((always_inline)) inline int64_t tile_off(int m, int k, int KS) {
   return ((int64_t)(m >> 4) * KS + (k >> 2)) * 64 + (k & 3) * 16 + (m & 15);
 }
 __host__ __device__ inline int64_t tiled_doubles(int64_t M) {
-  return ((M + 15) / 16) * 16 * (((M + 3) / 4) * 4);
+  return ((M + 15) / 16) * 16 * (4 * (int64_t)tile_ks(M));
 }
 
 // ---- MO blocks -------------------------------------------------------------
@@ -145,6 +175,20 @@ __global__ __launch_bounds__(256) void x_fold_kernel(const FragInfo* __restrict_
 
 // ---- pair solve --------------------------------------------------------------
 
+// Exact quotient x / d for 0 <= x < 2^22, 1 <= d < 2^11 through the FP32
+// reciprocal (the estimate is off by at most one, then corrected).
+struct FastDiv {
+  int d;
+  float r;
+  __device__ explicit FastDiv(int d_) : d(d_), r(1.0f / (float)d_) {}
+  __device__ __attribute__((always_inline)) int div(int x) const {
+    int q = (int)((float)x * r);
+    const int rem = x - q * d;
+    q += (rem >= d) - (rem < 0);
+    return q;
+  }
+};
+
 // One side of a Kronecker-sum GEMM: slice q of the block is
 // T[q * slice + (r0 + row) * ld + c0 + col].
 struct KronSide {
@@ -156,6 +200,12 @@ struct KronSide {
 // C[(al, al2)][(be, be2)] = s sum_{q < nq} X_q[al][al2] Y_q[be][be2] for al <
 // na, al2 < na2, be < nb, be2 < nb2 on FP64 MFMA; each element is handed to
 // store(al, al2, be, be2, value).  Waves take 32 x 32 output blocks in turn.
+// The q loop runs in chunks of kKronKC MFMA k steps, an even number of them,
+// two register buffers deep (the next chunk's loads are in flight while the
+// current one is multiplied).  Rows and columns past the block are clamped
+// into it (their results are dropped); q >= nq loads slice nq - 1 and
+// multiplies it by zero.
+constexpr int kKronKC = 5;
 template <class Store>
 __device__ __attribute__((always_inline)) inline void kron_gemm(const KronSide X, int na, int na2,
                                                                 const KronSide Y, int nb, int nb2,
@@ -165,35 +215,56 @@ __device__ __attribute__((always_inline)) inline void kron_gemm(const KronSide X
   const int RT2 = (nR + 31) >> 5, ST2 = (nS + 31) >> 5;
   const int li = lane & 15, lk = lane >> 4;
   const int nks = (nq + 3) >> 2;
+  const int nch = (((nks + kKronKC - 1) / kKronKC) + 1) & ~1;
+  const FastDiv da(na2), db(nb2);
   for (int task = wave; task < RT2 * ST2; task += kCgWaves) {
     const int rt = task / ST2, st = task - (task / ST2) * ST2;
     int64_t oa[2], ob[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int R = rt * 32 + u * 16 + li;
-      oa[u] = R < nR ? (int64_t)(X.r0 + R / na2) * X.ld + X.c0 + R % na2 : -1;
-      const int S = st * 32 + u * 16 + li;
-      ob[u] = S < nS ? (int64_t)(Y.r0 + S / nb2) * Y.ld + Y.c0 + S % nb2 : -1;
+      const int R = min(rt * 32 + u * 16 + li, nR - 1);
+      const int qa = da.div(R);
+      oa[u] = (int64_t)(X.r0 + qa) * X.ld + X.c0 + (R - qa * na2);
+      const int S = min(st * 32 + u * 16 + li, nS - 1);
+      const int qb = db.div(S);
+      ob[u] = (int64_t)(Y.r0 + qb) * Y.ld + Y.c0 + (S - qb * nb2);
     }
     d4v acc[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int w = 0; w < 2; ++w) acc[u][w] = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int ks = 0; ks < nks; ++ks) {
-      const int q = 4 * ks + lk;
-      const bool okq = q < nq;
-      double a[2], b[2];
+    double a0[kKronKC][2], b0[kKronKC][2], a1[kKronKC][2], b1[kKronKC][2];
+    auto load = [&](int ch, double (&a)[kKronKC][2], double (&b)[kKronKC][2])
+                    __attribute__((always_inline)) {
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        a[u] = okq && oa[u] >= 0 ? X.T[q * X.slice + oa[u]] : 0.0;
-        b[u] = okq && ob[u] >= 0 ? Y.T[q * Y.slice + ob[u]] : 0.0;
+      for (int j = 0; j < kKronKC; ++j) {
+        const int q = 4 * (ch * kKronKC + j) + lk;
+        const bool ok = q < nq;
+        const int64_t qc = ok ? q : nq - 1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const double av = X.T[qc * X.slice + oa[u]];
+          a[j][u] = ok ? av : 0.0;
+          b[j][u] = Y.T[qc * Y.slice + ob[u]];
+        }
       }
+    };
+    auto mult = [&](const double (&a)[kKronKC][2], const double (&b)[kKronKC][2])
+                    __attribute__((always_inline)) {
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int j = 0; j < kKronKC; ++j)
 #pragma unroll
-        for (int w = 0; w < 2; ++w) acc[u][w] = mma64(a[u], b[w], acc[u][w]);
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int w = 0; w < 2; ++w) acc[u][w] = mma64(a[j][u], b[j][w], acc[u][w]);
+    };
+    load(0, a0, b0);
+    for (int ch = 0; ch < nch; ch += 2) {
+      load(ch + 1, a1, b1);
+      mult(a0, b0);
+      if (ch + 2 < nch) load(ch + 2, a0, b0);
+      mult(a1, b1);
     }
     // FP64 MFMA result: row lk + 4 r, column li of each 16 x 16 tile
 #pragma unroll
@@ -203,8 +274,10 @@ __device__ __attribute__((always_inline)) inline void kron_gemm(const KronSide X
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int R = rt * 32 + u * 16 + lk + 4 * r, S = st * 32 + w * 16 + li;
-          if (R < nR && S < nS)
-            store(R / na2, R % na2, S / nb2, S % nb2, s * acc[u][w][r]);
+          if (R < nR && S < nS) {
+            const int qa = da.div(R), qb = db.div(S);
+            store(qa, R - qa * na2, qb, S - qb * nb2, s * acc[u][w][r]);
+          }
         }
   }
 }
@@ -212,7 +285,7 @@ __device__ __attribute__((always_inline)) inline void kron_gemm(const KronSide X
 // Zero the padding of a tiled M x M block: rows M .. 16 MT - 1 and columns
 // M .. 4 KS - 1 (the products read every element of a tile).
 __device__ __attribute__((always_inline)) inline void zero_tile_pad(double* A, int M) {
-  const int MT = (M + 15) >> 4, KS = (M + 3) >> 2;
+  const int MT = (M + 15) >> 4, KS = tile_ks(M);
   const int rows = MT * 16 - M, cols = KS * 4 - M;
   for (int e = threadIdx.x; e < rows * KS * 4; e += kCgThreads) {
     const int m = M + e / (KS * 4), k = e % (KS * 4);
@@ -226,45 +299,65 @@ __device__ __attribute__((always_inline)) inline void zero_tile_pad(double* A, i
 
 // out (op)= A p for one operator block: A is M x M in MFMA tiles; the product
 // B(k, n) = p[rp[k] + cp[n]] (n < N); each result goes to out[rp[m] + cp[n]]:
-//   mode 0: out = D * p + result there (the first block), 1: out += result,
-//   2: out -= result.
-// Waves take (row tile, two column tiles) tasks in turn.
+//   mode 0: out = result (the first block), 1: out += result, 2: out -= result.
+// Waves take (row tile, two column tiles) tasks in turn.  The tiles stream
+// in chunks of kApplyKC k steps, two register buffers deep; past the block,
+// k and n are clamped into it (A's padding columns are zero, results of
+// padding columns are dropped), so every load is unconditional.
 template <typename PV>
 __device__ __attribute__((always_inline)) inline void apply_block(
     const double* __restrict__ A, int M, int N, const int* rp, const int* cp, const PV* p,
-    PV* out, const double* __restrict__ D, int mode, int wave, int lane) {
-  const int MT = (M + 15) >> 4, KS = (M + 3) >> 2, NT2 = (N + 31) >> 5;
+    PV* out, int mode, int wave, int lane) {
+  const int MT = (M + 15) >> 4, KS = tile_ks(M), NT2 = (N + 31) >> 5;
   const int li = lane & 15, lk = lane >> 4;
   for (int task = wave; task < MT * NT2; task += kCgWaves) {
     const int mt = task / NT2, nt = task - (task / NT2) * NT2;
-    int c[2];
+    int cl[2];
+    bool okc[2];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
       const int n = nt * 32 + w * 16 + li;
-      c[w] = n < N ? cp[n] : -1;
+      okc[w] = n < N;
+      cl[w] = cp[min(n, N - 1)];
     }
     d4v acc[2] = {d4v{0.0, 0.0, 0.0, 0.0}, d4v{0.0, 0.0, 0.0, 0.0}};
     const double* At = A + (int64_t)mt * KS * 64 + lane;
-#pragma unroll 8
-    for (int ks = 0; ks < KS; ++ks) {
-      const double a = At[(int64_t)ks * 64];
-      const int k = 4 * ks + lk;
-      const int rk = k < M ? rp[k] : -1;
+    double a0[kApplyKC], a1[kApplyKC];
+    auto load = [&](int ks0, double (&a)[kApplyKC]) __attribute__((always_inline)) {
 #pragma unroll
-      for (int w = 0; w < 2; ++w) {
-        const double b = rk >= 0 && c[w] >= 0 ? (double)p[rk + c[w]] : 0.0;
-        acc[w] = mma64(a, b, acc[w]);
-      }
+      for (int j = 0; j < kApplyKC; ++j) a[j] = At[(int64_t)(ks0 + j) * 64];
+    };
+    auto mult = [&](int ks0, const double (&a)[kApplyKC]) __attribute__((always_inline)) {
+      int rk[kApplyKC];
+#pragma unroll
+      for (int j = 0; j < kApplyKC; ++j) rk[j] = rp[min(4 * (ks0 + j) + lk, M - 1)];
+      double b[kApplyKC][2];
+#pragma unroll
+      for (int j = 0; j < kApplyKC; ++j)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) b[j][w] = (double)p[rk[j] + cl[w]];
+#pragma unroll
+      for (int j = 0; j < kApplyKC; ++j)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) acc[w] = mma64(a[j], b[j][w], acc[w]);
+    };
+    load(0, a0);
+    for (int ks0 = 0; ks0 < KS; ks0 += 2 * kApplyKC) {
+      if (ks0 + kApplyKC < KS) load(ks0 + kApplyKC, a1);
+      mult(ks0, a0);
+      if (ks0 + kApplyKC >= KS) break;
+      if (ks0 + 2 * kApplyKC < KS) load(ks0 + 2 * kApplyKC, a0);
+      mult(ks0 + kApplyKC, a1);
     }
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-      if (c[w] < 0) continue;
+      if (!okc[w]) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = mt * 16 + lk + 4 * r;
         if (m >= M) continue;
-        const int e = rp[m] + c[w];
-        if (mode == 0) out[e] = fma(D[e], p[e], acc[w][r]);
+        const int e = rp[m] + cl[w];
+        if (mode == 0) out[e] = acc[w][r];
         else if (mode == 1) out[e] += acc[w][r];
         else out[e] -= acc[w][r];
       }
@@ -285,6 +378,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
     int32_t* __restrict__ iters, int32_t* __restrict__ flags) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ double red[kCgWaves];
+  __shared__ double red2[2][kCgWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int tid = threadIdx.x;
   double* slot = slots + (int64_t)blockIdx.x * L.size;
@@ -364,7 +458,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
     }
     // operator blocks
     {
-      const int KS = (nV + 3) >> 2;
+      const int KS = tile_ks(nV);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, ox, ox}, vx, vx, KronSide{Yy, nny, fy.nbf, oy, oy}, vy,
                 vy, P0, s, wave, lane,
                 [&](int a, int a2, int b, int b2, double val) __attribute__((always_inline)) {
@@ -373,7 +467,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       zero_tile_pad(Aq, nV);
     }
     {
-      const int KS = (nPH + 3) >> 2;
+      const int KS = tile_ks(nPH);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, ox, ox}, vx, vx, KronSide{Yy, nny, fy.nbf, 0, 0}, oy,
                 oy, P0, s, wave, lane,
                 [&](int a, int a2, int j, int j2, double val) __attribute__((always_inline)) {
@@ -382,7 +476,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       zero_tile_pad(Aph, nPH);
     }
     {
-      const int KS = (nHP + 3) >> 2;
+      const int KS = tile_ks(nHP);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, 0, 0}, ox, ox, KronSide{Yy, nny, fy.nbf, oy, oy}, vy,
                 vy, P0, s, wave, lane,
                 [&](int i, int i2, int b, int b2, double val) __attribute__((always_inline)) {
@@ -391,7 +485,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       zero_tile_pad(Ahp, nHP);
     }
     {
-      const int KS = (nO + 3) >> 2;
+      const int KS = tile_ks(nO);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, 0, 0}, ox, ox, KronSide{Yy, nny, fy.nbf, 0, 0}, oy,
                 oy, P0, s, wave, lane,
                 [&](int i, int i2, int j, int j2, double val) __attribute__((always_inline)) {
@@ -401,20 +495,25 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
     }
     __syncthreads();
 
-    // (D + W) p into apb
+    // W p into apb (the owner of each element adds D p)
     auto apply = [&]() __attribute__((always_inline)) {
-      apply_block(Aq, nV, nO, rp_pp, cp_pp, pb, apb, D, 0, wave, lane);
+      apply_block(Aq, nV, nO, rp_pp, cp_pp, pb, apb, 0, wave, lane);
       __syncthreads();
-      apply_block(Aph, nPH, nHP, rp_ph, cp_ph, pb, apb, D, 2, wave, lane);
+      apply_block(Aph, nPH, nHP, rp_ph, cp_ph, pb, apb, 2, wave, lane);
       __syncthreads();
-      apply_block(Ahp, nHP, nPH, rp_hp, cp_hp, pb, apb, D, 2, wave, lane);
+      apply_block(Ahp, nHP, nPH, rp_hp, cp_hp, pb, apb, 2, wave, lane);
       __syncthreads();
-      apply_block(Ahh, nO, nV, rp_hh, cp_hh, pb, apb, D, 1, wave, lane);
+      apply_block(Ahh, nO, nV, rp_hh, cp_hh, pb, apb, 1, wave, lane);
       __syncthreads();
     };
 
-    // start: t = b / D with b = -v; r = b - (D + W) t; p = z = r / D
+    // start: t = b / D with b = -v; r = b - (D + W) t; p = z = r / D.
+    // Conjugate gradients as the oracle takes them; t, r and D live in the
+    // slot, p and W p in LDS when they fit.
+    double nb, rr, vt = 0.0;
+    int it = 0;
     double bb = 0.0;
+#pragma unroll 4
     for (int e = tid; e < n; e += kCgThreads) {
       const double b = -v[e];
       const double t0 = b / D[e];
@@ -422,45 +521,51 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       pb[e] = t0;
       bb = fma(b, b, bb);
     }
-    const double nb = sqrt(block_sum(bb, red));
+    nb = sqrt(block_sum(bb, red));
     apply();
-    double rz = 0.0, rr = 0.0;
+    double rz = 0.0;
+    rr = 0.0;
+#pragma unroll 4
     for (int e = tid; e < n; e += kCgThreads) {
-      const double re = -v[e] - apb[e];
+      const double re = -v[e] - fma(D[e], pb[e], apb[e]);
       const double z = re / D[e];
       r[e] = re;
       pb[e] = z;
       rz = fma(re, z, rz);
       rr = fma(re, re, rr);
     }
-    rz = block_sum(rz, red);
-    rr = block_sum(rr, red);
-    int it = 0;
+    block_sum_pair(rz, rr, red2);
     while (it < maxit && !(sqrt(rr) <= tol * nb)) {
       apply();
       double pap = 0.0;
-      for (int e = tid; e < n; e += kCgThreads) pap = fma(pb[e], apb[e], pap);
+#pragma unroll 4
+      for (int e = tid; e < n; e += kCgThreads) {
+        const double pe = pb[e];
+        pap = fma(pe, fma(D[e], pe, apb[e]), pap);
+      }
       pap = block_sum(pap, red);
       const double alpha = rz / pap;
       double rzn = 0.0;
       rr = 0.0;
+#pragma unroll 4
       for (int e = tid; e < n; e += kCgThreads) {
-        t[e] = fma(alpha, pb[e], t[e]);
-        const double re = fma(-alpha, apb[e], r[e]);
+        const double pe = pb[e];
+        t[e] = fma(alpha, pe, t[e]);
+        const double re = fma(-alpha, fma(D[e], pe, apb[e]), r[e]);
         r[e] = re;
         const double z = re / D[e];
         rzn = fma(re, z, rzn);
         rr = fma(re, re, rr);
       }
-      rzn = block_sum(rzn, red);
-      rr = block_sum(rr, red);
+      block_sum_pair(rzn, rr, red2);
       const double beta = rzn / rz;
+#pragma unroll 4
       for (int e = tid; e < n; e += kCgThreads) pb[e] = fma(beta, pb[e], r[e] / D[e]);
       rz = rzn;
       ++it;
       __syncthreads();
     }
-    double vt = 0.0;
+#pragma unroll 4
     for (int e = tid; e < n; e += kCgThreads) vt = fma(v[e], t[e], vt);
     const double E = 4.0 * block_sum(vt, red);
     if (tid == 0) {
@@ -519,8 +624,9 @@ void coupled_setup(fef_plan_s& p) {
       p.cp_list.push_back(k);
     }
     const int64_t tab_bytes = 8 * (nV + nO + nPH + nHP);
-    g.lds = 16 * nmax + tab_bytes <= kCgLdsMax - 1024;
-    g.lds_bytes = (size_t)(g.lds ? 16 * nmax + tab_bytes : tab_bytes);
+    const int64_t lds_bytes = 16 * nmax + tab_bytes;
+    g.lds = lds_bytes <= kCgLdsMax - 1024;
+    g.lds_bytes = (size_t)(g.lds ? lds_bytes : tab_bytes);
     auto al = [](int64_t x) { return round_up(std::max<int64_t>(x, 1), 64); };
     CgSlot& L = g.L;
     int64_t o = 0;
@@ -617,6 +723,8 @@ fef_status fef_coupled_pair_energies(fef_plan p, const double* B, const double* 
   if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return FEF_E_ARG;
   if (p->npair > 0 && (!B || !C || !eps || !G || !E2_pair || !ws)) return FEF_E_ARG;
   if (p->npair > 0 && ws_bytes < (size_t)coupled_ws_bytes(*p)) return FEF_E_WORKSPACE;
+  // index arithmetic of the blocks is exact below nbf = 2048
+  if (p->max_nbf >= 2048) return FEF_E_UNSUPPORTED;
   for (const auto& g : p->cp_groups)
     if (g.lds_bytes > (size_t)kCgLdsMax) return FEF_E_UNSUPPORTED;
   coupled_prepare();
