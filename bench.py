@@ -25,6 +25,12 @@ Each mode also reports the half transform + pair energies unit on the final
 orbitals on its own: 25 event-timed repetitions, the first 5 discarded,
 median / min / max.
 
+The coupled dimer doubles (W^[0] in H0, fef_coupled_pair_energies) are
+timed on the same box and orbitals as a block of their own ("coupled"): one
+warm call, then event-timed calls; their roofline counts the FP64 flops of
+the operator blocks and of every product W p the solves took (the iteration
+counts come back from the call).
+
 Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
 """
@@ -63,6 +69,8 @@ def parse():
     ap.add_argument("--surrogate-threshold", type=float, default=1e-8,
                     help="ensemble spread (Eh) above which a pair falls back to the exact kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true",
+                    help="skip the coupled dimer-doubles block")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration)")
@@ -186,6 +194,60 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
             "sample": f"1 FP64 SCF step over all {sysm.nfrag} fragments ({t_scf:.2f} s) and "
                       f"{done} random pairs ({t_pairs:.2f} s), scaled to {niter} SCF steps + "
                       f"all {sysm.npair} pairs"}
+
+
+def coupled_flops(sysm, iters) -> float:
+    """Algorithmic FP64 flops of the coupled solves: per pair the five
+    Kronecker-sum blocks (v and the four W blocks, 2 P0 flops per element)
+    and (iterations + 1) products W p (2 flops per block element per
+    amplitude column)."""
+    x, y = sysm.pair_x, sysm.pair_y
+    ox, oy = sysm.nocc[x].astype(np.float64), sysm.nocc[y].astype(np.float64)
+    vx, vy = sysm.nbf[x] - sysm.nocc[x], sysm.nbf[y] - sysm.nocc[y]
+    vx, vy = vx.astype(np.float64), vy.astype(np.float64)
+    P0 = float(sysm.naux_class[0])
+    nV, nO, nPH, nHP = vx * vy, ox * oy, vx * oy, ox * vy
+    build = 2 * P0 * (ox * vx * oy * vy + nV ** 2 + nPH ** 2 + nHP ** 2 + nO ** 2)
+    apply = 2 * (nV ** 2 * nO + nPH ** 2 * nHP + nHP ** 2 * nPH + nO ** 2 * nV)
+    return float(np.sum(build + (np.asarray(iters, dtype=np.float64) + 1) * apply))
+
+
+def bench_coupled(ctx, sysm, torch, st, reps: int = 2):
+    """The coupled pair solves (FP64 MFMA) on the current orbitals."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    _, _, it = ctx.coupled_pair_energies()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = ev(), ev()
+        a.record(st)
+        E, tot, it = ctx.coupled_pair_energies()
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    iters = it.cpu().numpy()
+    t = float(np.mean(ms))
+    flops = coupled_flops(sysm, iters)
+    return {"ms": round(t, 3), "reps": reps, "pairs_per_s": sysm.npair / (t / 1e3),
+            "E2_total": float(tot.item()), "flags": int(ctx.flags.item()),
+            "iters_mean": float(iters.mean()) if len(iters) else 0.0,
+            "iters_max": int(iters.max()) if len(iters) else 0,
+            "roofline": {"kernel": "coupled pair solve (FP64 MFMA)", "bound": "mfma",
+                         "achieved": flops / (t / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": flops / (t / 1e3) / 78.6e12, "algorithmic_flops": flops,
+                         "note": "whole call (MO blocks, per-pair build and solve, total)"}}
+
+
+def coupled_cpu_baseline(sysm, C, eps, npairs: int = 8):
+    """The coupled oracle on a few pairs of the same box and orbitals."""
+    from oracle import coupled as oc
+    idx = np.random.default_rng(1).choice(sysm.npair, size=min(npairs, sysm.npair),
+                                          replace=False)
+    t0 = time.perf_counter()
+    oc.coupled_pair_energies(sysm, C, eps, pairs=[int(k) for k in idx])
+    dt = time.perf_counter() - t0
+    return {"value": len(idx) / dt, "unit": "pairs/s", "kind": "oracle",
+            "sample": f"{len(idx)} random pairs, CG to 1e-14 ({dt:.2f} s)"}
 
 
 # pair modes timed per workload when --modes is not given
@@ -427,6 +489,11 @@ def main():
 
     print("[bench] SCF stages", file=sys.stderr, flush=True)
     scf_stages = bench_scf_stages(ctx, lib, sysm)
+    coupled = None
+    if not args.no_coupled:
+        print("[bench] coupled dimer doubles", file=sys.stderr, flush=True)
+        coupled = bench_coupled(ctx, sysm, torch, st)
+        coupled_C, coupled_eps = ctx.C.cpu().numpy(), ctx.eps.cpu().numpy()
     ref = results["f64"]
     ref_oracle = oracle_total(spec.name)
     ref_total = ref_oracle if ref_oracle is not None else ref["E_total"]
@@ -510,6 +577,7 @@ def main():
         "accuracy_gate": {"bar_Eh": TOTAL_ERR_BAR, "against": "oracle" if ref_oracle is not None
                           else "gpu_f64", "oracle_total": ref_oracle},
         "scf_roofline": scf_stages,
+        "coupled": coupled,
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],
         "speedup_vs_fp64": h["pairs_per_s"] / modes_out["f64"]["pairs_per_s"],
         "modes": modes_out,
@@ -517,6 +585,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sysm, niter, args.cpu_seconds)
+        if coupled is not None:
+            coupled["cpu_baseline"] = coupled_cpu_baseline(sysm, coupled_C, coupled_eps)
     print(json.dumps(line), flush=True)
 
 

@@ -5,6 +5,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -58,3 +60,16 @@ def test_scf_stage_model_config0():
     assert m["field_bytes"] == 8 * 8 * 72 * tri + 8 * 8 * 72 + 8 * s.G.size + 2 * nn + (
         nn if s.htilde is not None else 0)
     assert m["eigh_flops"] == 8 * (9.0 * 24 ** 3 + 2.0 * 24 * 24 * 5)
+
+
+def test_coupled_flops_counts_blocks_and_products():
+    """Water pair (ox = oy = 5, vx = vy = 19, P0 = 72): five Kronecker-sum
+    blocks and (iterations + 1) products of the four W blocks."""
+    import types
+    import bench
+    sysm = types.SimpleNamespace(pair_x=np.array([0]), pair_y=np.array([1]),
+                                 nocc=np.array([5, 5]), nbf=np.array([24, 24]),
+                                 naux_class=np.array([72]))
+    build = 2 * 72 * (95 * 95 + 361 ** 2 + 95 ** 2 + 95 ** 2 + 25 ** 2)
+    apply = 2 * (361 ** 2 * 25 + 95 ** 2 * 95 * 2 + 25 ** 2 * 361)
+    assert bench.coupled_flops(sysm, [8]) == build + 9 * apply
