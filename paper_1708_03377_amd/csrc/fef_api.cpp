@@ -489,7 +489,8 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
                                 double* D, double* dD_max, int32_t* flags, void* ws,
                                 size_t ws_bytes, void* stream, const double* B_pack = nullptr,
                                 double* Bp_out = nullptr, bool carry_out = false,
-                                const double* Dprev = nullptr, double* Dout = nullptr) {
+                                const double* Dprev = nullptr, double* Dout = nullptr,
+                                bool moments_in = false, bool moments_out = false) {
   if (!p) return FEF_E_ARG;
   if (!dD_max || !flags) return FEF_E_ARG;
   if (p->nfrag > 0 && (!(B || Bp) || !G || !F0 || !C || !eps)) return FEF_E_ARG;
@@ -501,6 +502,11 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   // with a carried density the moments kernel clears the maximum that the
   // eigensolver accumulates (no kernel of its own)
   const bool clear_in_moments = Dprev && Bp && p->nfrag > 0;
+  // moments_in: the previous step's eigensolver left this step's moments in
+  // the workspace (no moments kernel; the field kernel clears the maximum);
+  // moments_out: this step's eigensolver leaves the next step's there
+  moments_in = moments_in && clear_in_moments;
+  moments_out = moments_out && carry_out && Bp && p->nfrag > 0;
   stage_mark(*p, 0, st);
   hipError_t e = !Dprev ? launch_density(*p, C, w.Dold, Bp ? w.Dw : nullptr, dD_max, st)
                  : clear_in_moments ? hipSuccess
@@ -508,12 +514,13 @@ static fef_status scf_step_impl(fef_plan p, const double* B, const double* Bp, c
   stage_mark(*p, 1, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = Bp ? launch_field_packed(*p, Bp, G, w.Dw, F0, htilde, w.F, w.wd, w.wphi, st, B_pack,
-                                 Bp_out, clear_in_moments ? dD_max : nullptr)
+                                 Bp_out, clear_in_moments ? dD_max : nullptr, moments_in)
            : launch_field(*p, B, G, Dold, F0, htilde, w.F, w.wd, w.wphi, st);
   stage_mark(*p, 3, st);
   if (e == hipSuccess && p->nfrag > 0)
     e = launch_eigh(*p, w.F, Dold, C, eps, Dnew, dD_max, flags, w.eigws, st,
-                    carry_out ? w.Dw : nullptr);
+                    carry_out ? w.Dw : nullptr, moments_out ? (Bp_out ? Bp_out : Bp) : nullptr,
+                    moments_out ? w.wd : nullptr);
   stage_mark(*p, 4, st);
   return hip_status(e);
 }
@@ -579,6 +586,15 @@ fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const doubl
 
 bool density_carry_ok(const fef_plan_s& p) { return p.max_nbf <= 32; }
 
+bool moments_carry_ok(const fef_plan_s& p) {
+  if (!density_carry_ok(p) || !small_fragments(p)) return false;
+  for (const FragInfo& fi : p.frag) {
+    const int nt = fi.nbf * (fi.nbf + 1) / 2;
+    if ((nt & 1) != 0 || nt > 384) return false;
+  }
+  return true;
+}
+
 fef_status scf_step_carry(fef_plan p, const double* B_pack, double* Bp, const double* G,
                           const double* F0, const double* htilde, double* C, double* eps,
                           double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,
@@ -591,9 +607,13 @@ fef_status scf_step_carry(fef_plan p, const double* B_pack, double* Bp, const do
   // last step's lands in D and no step reads the pool it writes
   double* spare = scf_ws(*p, ws).Dspare;
   auto target = [&](int s) { return ((nsteps - 1 - s) % 2 == 0) ? D : spare; };
+  // with moments_carry_ok every step but the last also forms the next
+  // step's moments in its eigensolver, and every step but the first uses them
+  const bool mc = moments_carry_ok(*p);
   return scf_step_impl(p, nullptr, Bp, G, F0, htilde, C, eps, D, dD_max, flags, ws, ws_bytes,
                        stream, B_pack, B_pack ? Bp : nullptr, true,
-                       step > 0 ? target(step - 1) : nullptr, target(step));
+                       step > 0 ? target(step - 1) : nullptr, target(step), mc && step > 0,
+                       mc && step + 1 < nsteps);
 }
 
 }  // namespace fef

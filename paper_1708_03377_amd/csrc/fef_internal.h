@@ -237,9 +237,13 @@ hipError_t launch_field(const fef_plan_s& p, const double* B, const double* G,
 // Dw non-null (only when every fragment has nbf <= 32): the register-
 // resident solvers also write the weighted packed density of the new
 // orbitals, bitwise as launch_density forms it, for the next step
+// Bp and dmom non-null (moments_carry_ok only, with Dw): the register-resident
+// solvers also leave the Coulomb moments of the new densities in dmom,
+// bitwise as the packed moments kernel forms them, for the next step
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
                        double* C, double* eps, double* Dnew, double* dD_max,
-                       int32_t* flags, double* ws_eig, hipStream_t st, double* Dw = nullptr);
+                       int32_t* flags, double* ws_eig, hipStream_t st, double* Dw = nullptr,
+                       const double* Bp = nullptr, double* dmom = nullptr);
 hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* Dold, double* C,
                            double* eps, double* Dnew, double* dD_max, int32_t* flags,
                            double* ws_eig, hipStream_t st);
@@ -258,7 +262,7 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st,
                                const double* B_pack = nullptr, double* Bp_out = nullptr,
-                               double* zero_out = nullptr);
+                               double* zero_out = nullptr, bool moments_given = false);
 hipError_t launch_moments(const fef_plan_s& p, const double* B, const double* D, double* dmom,
                           hipStream_t st);
 // One packed SCF step that also writes the packed copy Bp of B (its moments
@@ -275,6 +279,11 @@ fef_status scf_step_packing(fef_plan p, const double* B, double* Bp, const doubl
 // no density kernel.  The densities alternate between a spare workspace
 // pool and D, the last step's landing in D.  Same results as packed steps.
 bool density_carry_ok(const fef_plan_s& p);
+// the carried steps also carry the Coulomb moments (the eigensolver of one
+// step forms those of the next): every fragment small enough for the
+// register-resident eigensolver and the fused field kernel, with an even
+// packed triangle of at most 384 numbers
+bool moments_carry_ok(const fef_plan_s& p);
 fef_status scf_step_carry(fef_plan p, const double* B_pack, double* Bp, const double* G,
                           const double* F0, const double* htilde, double* C, double* eps,
                           double* D, double* dD_max, int32_t* flags, void* ws, size_t ws_bytes,

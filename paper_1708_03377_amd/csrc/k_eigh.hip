@@ -348,12 +348,17 @@ __device__ inline double bperm_d(int byte_addr, double x) {
 // Bounded to two waves per SIMD (at most 256 registers): the 4000-matrix
 // batches then fit on the chip at once, and the two waves of a SIMD hide
 // each other's latency in the round's dependent chain.
+// slices per group of the fused moments (the packed moments kernel's kMomQW)
+constexpr int kMomQWave = 8;
+
 template <int M>
 __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ list, int32_t count,
     const double* __restrict__ F, const double* __restrict__ Dold, double* __restrict__ C,
     double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
-    int32_t* __restrict__ flags, const int64_t* __restrict__ off_tri, double* __restrict__ Dw) {
+    int32_t* __restrict__ flags, const int64_t* __restrict__ off_tri, double* __restrict__ Dw,
+    const double* __restrict__ Bp, const int64_t* __restrict__ off_Bp,
+    double* __restrict__ dmom) {
   static_assert(M % 2 == 0 && M >= 2 && M <= 32, "half-wave matrix size");
   constexpr int LD = M + 1;
   __shared__ double S1[2][M * LD];
@@ -537,14 +542,69 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
         }
         Dnew[oc + t * n + j] = acc;
         // the weighted packed copy, exactly as the density kernel forms it
-        if (Dw && t <= j)
-          Dw[off_tri[f] + t * n - t * (t - 1) / 2 + (j - t)] = (t == j ? 1.0 : 2.0) * acc;
+        if (Dw && t <= j) {
+          const int kk = t * n - t * (t - 1) / 2 + (j - t);
+          const double w = (t == j ? 1.0 : 2.0) * acc;
+          Dw[off_tri[f] + kk] = w;
+          if (dmom) s2[kk] = w;
+        }
         dmax = fmax(dmax, fabs(acc - dold[j]));
       }
     }
   }
 #pragma unroll
   for (int o = 16; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, 32));
+  if (dmom) {
+    // Coulomb moments of the new densities for the next SCF step, d_Q =
+    // sum_k Bp[Q][k] Dw[k], computed here as the packed moments kernel
+    // computes them (the whole wave per matrix, lane l holding positions
+    // 2 l + 128 c, c = 0..2, eight slices at a time, the same products in the
+    // same order and the same wave sum), so the values are bitwise equal.
+    // Only launched when every triangle is even-sized, at most 384 numbers
+    // and starts at even offsets (the packed kernel's direct path).
+    __syncthreads();
+#pragma unroll 1
+    for (int hh = 0; hh < 2; ++hh) {
+      const int mj = blockIdx.x * 2 + hh;
+      if (mj >= count) break;
+      const int fj = list[mj];
+      const FragInfo fi = frag[fj];
+      const int nt = fi.nbf * (fi.nbf + 1) / 2;
+      const double* dl = S2[hh];
+      double2 dv[3];
+      int kc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int k = 2 * lane + 128 * c;
+        kc[c] = min(k, nt - 2);
+        dv[c] = k < nt ? double2{dl[k], dl[k + 1]} : double2{0.0, 0.0};
+      }
+#pragma unroll 1
+      for (int q0 = 0; q0 < fi.naux; q0 += kMomQWave) {
+        const int nq = min(kMomQWave, fi.naux - q0);
+        const double* b = Bp + off_Bp[fj] + (int64_t)q0 * nt;
+        double2 bv[kMomQWave][3];
+#pragma unroll
+        for (int q = 0; q < kMomQWave; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            bv[q][c] = *reinterpret_cast<const double2*>(b + (int64_t)min(q, nq - 1) * nt + kc[c]);
+        double accm[kMomQWave];
+#pragma unroll
+        for (int q = 0; q < kMomQWave; ++q) {
+          accm[q] = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            accm[q] = fma(bv[q][c].y, dv[c].y, fma(bv[q][c].x, dv[c].x, accm[q]));
+        }
+#pragma unroll
+        for (int q = 0; q < kMomQWave; ++q) {
+          const double tq = wave_sum_dpp(accm[q]);
+          if (lane == 0 && q < nq) dmom[fi.off_aux + q0 + q] = tq;
+        }
+      }
+    }
+  }
   if (active && t == 0) {
     atomic_max_nonneg(dD_max, dmax);
     if (nocc > 0 && nocc < n) {
@@ -780,7 +840,8 @@ static size_t eig_scratch_bytes(int n) {
 
 hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold, double* C,
                        double* eps, double* Dnew, double* dD_max, int32_t* flags,
-                       double* ws_eig, hipStream_t st, double* Dw) {
+                       double* ws_eig, hipStream_t st, double* Dw, const double* Bp,
+                       double* dmom) {
   // n <= 32: register-resident kernels, one size class per launch
   {
     const int sizes[4] = {8, 16, 24, 32};
@@ -791,7 +852,7 @@ hipError_t launch_eigh(const fef_plan_s& p, const double* F, const double* Dold,
       const int32_t* lst = p.d_eig_small + b;
 #define FEF_EIGW(MM)                                                                          \
   hipLaunchKernelGGL((eigh_wave_kernel<MM>), grid, dim3(64), 0, st, p.d_frag, lst, cnt, F,    \
-                     Dold, C, eps, Dnew, dD_max, flags, p.d_off_tri, Dw)
+                     Dold, C, eps, Dnew, dD_max, flags, p.d_off_tri, Dw, Bp, p.d_off_Bp, dmom)
       switch (sizes[c]) {
         case 8: FEF_EIGW(8); break;
         case 16: FEF_EIGW(16); break;

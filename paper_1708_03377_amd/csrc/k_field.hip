@@ -468,8 +468,12 @@ __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
     const double* __restrict__ G, const int64_t* __restrict__ off_G, int P0, int nclass,
     const int32_t* __restrict__ naux_cls_off, const double* __restrict__ dmom,
     const int64_t* __restrict__ off_Bp, const double* __restrict__ Bp,
-    const double* __restrict__ F0, const double* __restrict__ htilde, double* __restrict__ out) {
+    const double* __restrict__ F0, const double* __restrict__ htilde, double* __restrict__ out,
+    double* __restrict__ zero_out) {
   extern __shared__ double part[];  // [NW][etot] per-wave partial e_c, then e; then phi^x
+  // zero_out non-null: one thread clears it (a maximum that a later kernel
+  // of the same step accumulates; set when no moments kernel runs)
+  if (zero_out && blockIdx.x == 0 && threadIdx.x == 0) *zero_out = 0.0;
   const int NW = blockDim.x >> 6;
   // fragments in reverse order: the moments kernel before it streamed the
   // slices forwards, so the last ones it read are the first ones read here
@@ -692,16 +696,21 @@ hipError_t launch_pack_coefficients(const fef_plan_s& p, const double* B, double
 hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const double* G,
                                const double* Dw, const double* F0, const double* htilde,
                                double* out, double* ws_d, double* ws_phi, hipStream_t st,
-                               const double* B_pack, double* Bp_out, double* zero_out) {
+                               const double* B_pack, double* Bp_out, double* zero_out,
+                               bool moments_given) {
   const int nqb = (p.max_naux + 4 * kMomQW - 1) / (4 * kMomQW);
   const dim3 mgrid((unsigned)((int64_t)p.nfrag * nqb));
-  if (B_pack)
+  if (moments_given) {
+    // ws_d already holds the moments (left there by the previous step's
+    // eigensolver); the fused field kernel clears zero_out instead
+  } else if (B_pack)
     hipLaunchKernelGGL(moments_packed_kernel<true>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
                        p.d_off_tri, nullptr, Dw, ws_d, B_pack, Bp_out, nqb, zero_out);
   else
     hipLaunchKernelGGL(moments_packed_kernel<false>, mgrid, dim3(256), 0, st, p.d_frag, p.d_off_Bp,
                        p.d_off_tri, Bp, Dw, ws_d, nullptr, nullptr, nqb, zero_out);
   stage_mark(p, 2, st);
+  if (moments_given && !small_fragments(p)) return hipErrorInvalidValue;
   const int etot = p.naux_cls_off.back();
   const int ntmax = p.max_nbf * (p.max_nbf + 1) / 2;
   if (small_fragments(p)) {
@@ -710,7 +719,8 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
     const size_t lds = ((size_t)(jt / 64) * etot + p.max_naux) * sizeof(double);
     hipLaunchKernelGGL(field_jbuild_packed_kernel, dim3(p.nfrag), dim3(jt), lds, st, p.d_frag,
                        p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
-                       p.d_naux_cls_off, ws_d, p.d_off_Bp, Bp, F0, htilde, out);
+                       p.d_naux_cls_off, ws_d, p.d_off_Bp, Bp, F0, htilde, out,
+                       moments_given ? zero_out : nullptr);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(field_kernel, dim3(p.nfrag), dim3(256), 4 * etot * sizeof(double), st, p.d_frag,
