@@ -85,11 +85,15 @@ __host__ __device__ constexpr int split_nterm(int prec) { return prec == FEF_BF1
 // Eigensolver workspace (doubles) per fragment with nbf > 48, for the
 // largest such nbf: the Jacobi path keeps V^T and a product matrix
 // (2 (n + 1)^2), the tridiagonal path T (three vectors), the packed
-// reflectors and the eigenvectors of T (rows padded to n + 64 columns).
+// reflectors, the eigenvectors of T (rows padded to n + 64 columns) and the
+// reflectors expanded in blocks of four for the back-transformation (rows
+// of kTriVbStride, then 16 Gram entries per block).
+constexpr int kTriVbStride = 152;
 __host__ __device__ inline int64_t eig_large_slot(int nmax) {
   const int64_t jac = 2 * (int64_t)(nmax + 1) * (nmax + 1);
+  const int64_t nb = nmax > 2 ? (nmax - 2 + 3) / 4 : 0;
   const int64_t tri = 3 * (int64_t)nmax + (int64_t)nmax * (nmax + 1) / 2 +
-                      (int64_t)nmax * (nmax + 64);
+                      (int64_t)nmax * (nmax + 64) + nb * (4 * kTriVbStride + 16);
   return jac > tri ? jac : tri;
 }
 // Largest nbf of the tridiagonal (Householder) eigensolver.

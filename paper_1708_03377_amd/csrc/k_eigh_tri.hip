@@ -121,10 +121,13 @@ __device__ inline double start_entry(int j, int i) {
 
 // Per-matrix workspace (doubles, a slot of eig_large_slot(max_n)):
 //   T: d [n], e [n], tau [n]; the reflectors, packed [refl_off(n - 2, n)];
-//   Z [n][n + 64] (row j = eigenvector j of T, zero past n).
+//   Z [n][n + 64] (row j = eigenvector j of T, zero past n); the reflector
+//   blocks of the back-transformation expanded, VB [nb][kBackBlock]
+//   [kTriVbStride], and their Gram entries GB [nb][16].
 struct TriWs {
-  double *d, *e, *tau, *refl, *Z;
+  double *d, *e, *tau, *refl, *Z, *VB, *GB;
 };
+__device__ inline int back_blocks(int n) { return n >= 3 ? (n - 2 + kBackBlock - 1) / kBackBlock : 0; }
 __device__ inline TriWs tri_ws(double* ws_eig, int max_n, int n) {
   TriWs w;
   w.d = ws_eig + (size_t)blockIdx.x * eig_large_slot(max_n);
@@ -132,6 +135,8 @@ __device__ inline TriWs tri_ws(double* ws_eig, int max_n, int n) {
   w.tau = w.e + n;
   w.refl = w.tau + n;
   w.Z = w.refl + (n > 2 ? refl_off(n - 2, n) : 0);
+  w.VB = w.Z + (size_t)n * (n + 64);
+  w.GB = w.VB + (size_t)back_blocks(n) * kBackBlock * kTriVbStride;
   return w;
 }
 
@@ -532,26 +537,84 @@ __global__ __launch_bounds__(64) void eigh_tri_vectors_kernel(
 
 // ---------------------------------------------------------------------------
 // 3. back-transformation and outputs
+//
+// The eigenvectors z of T go back through the reflectors, C = H_0 H_1 ...
+// H_{n-3} Z, four reflectors per step.  Block b holds reflectors r_i = k0 -
+// i, i < kBackBlock, k0 = n - 3 - kBackBlock b, applied in the order r_0,
+// r_1, ... (H_{r_0} first); a reflector index below 0 is a zero vector with
+// tau = 0.  With the Gram entries g_ij = v_i . v_j (i > j) and g_ii = tau_i,
+// the block maps z to z - sum_i y_i v_i with
+//   y_i = tau_i (v_i . z - sum_{j < i} g_ij y_j).
+// (a) eigh_tri_expand_kernel: one wave per block writes the expanded
+//     vectors (zeros outside r_i + 1 .. n - 1) and the Gram entries;
+// (b) eigh_tri_back_kernel: one wave per 32 eigenvectors (two lanes per
+//     eigenvector, as in the vector kernel) streams the blocks through LDS
+//     (the next block's copy issued before the current one is applied) and
+//     writes its columns of C;
+// (c) eigh_tri_density_kernel: D = C_occ C_occ^T, max |D - D_old| and the
+//     gap flag.
 template <int SEG>
-__global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
-    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
-    const double* __restrict__ Dold, double* __restrict__ C, const double* __restrict__ eps,
-    double* __restrict__ Dnew, double* __restrict__ dD_max, int32_t* __restrict__ flags,
-    double* __restrict__ ws_eig, int max_n) {
+__global__ __launch_bounds__(64) void eigh_tri_expand_kernel(const FragInfo* __restrict__ frag,
+                                                             const int32_t* __restrict__ list,
+                                                             double* __restrict__ ws_eig,
+                                                             int max_n) {
   constexpr int NC = kTriLanes * SEG;
-  extern __shared__ double sm[];  // the packed reflectors, later the occupied block
-  __shared__ double vbuf[2][kBackBlock][NC];  // a block of expanded reflectors
-  __shared__ double gbuf[2][kBackBlock * kBackBlock];  // tau_i, v_i . v_j (i > j)
-  __shared__ double red[kTriThreads / 64];
+  static_assert(NC <= kTriVbStride, "expanded reflector stride");
+  const int n = frag[list[blockIdx.x]].nbf;
+  const int b = blockIdx.y;
+  if (b >= back_blocks(n)) return;
+  const TriWs W = tri_ws(ws_eig, max_n, n);
+  const int lane = threadIdx.x;
+  const int k0 = n - 3 - kBackBlock * b;
+  double* dst = W.VB + (size_t)b * kBackBlock * kTriVbStride;
+  double* g = W.GB + (size_t)b * 16;
+  double vv[kBackBlock][(NC + 63) / 64];
+#pragma unroll
+  for (int i = 0; i < kBackBlock; ++i) {
+    const int k = k0 - i;
+    const double* vk = W.refl + (k >= 0 ? refl_off(k, n) - (k + 1) : 0);
+#pragma unroll
+    for (int u = 0; u < (NC + 63) / 64; ++u) {
+      const int j = lane + 64 * u;
+      const double x = (k >= 0 && j > k && j < n) ? vk[j] : 0.0;
+      vv[i][u] = x;
+      if (j < NC) dst[i * kTriVbStride + j] = x;
+    }
+  }
+#pragma unroll
+  for (int i = 1; i < kBackBlock; ++i)
+#pragma unroll
+    for (int jj = 0; jj < i; ++jj) {
+      double d = 0.0;
+#pragma unroll
+      for (int u = 0; u < (NC + 63) / 64; ++u)
+        if (lane + 64 * u < NC) d = fma(vv[i][u], vv[jj][u], d);
+      d = wave_sum_dpp(d);
+      if (lane == 0) g[i * kBackBlock + jj] = d;
+    }
+  if (lane < kBackBlock) {
+    const int k = k0 - lane;
+    g[lane * kBackBlock + lane] = k >= 0 ? W.tau[k] : 0.0;
+  }
+}
+
+template <int SEG>
+__global__ __launch_bounds__(64) void eigh_tri_back_kernel(const FragInfo* __restrict__ frag,
+                                                           const int32_t* __restrict__ list,
+                                                           double* __restrict__ C,
+                                                           double* __restrict__ ws_eig,
+                                                           int max_n) {
+  constexpr int NC = kTriLanes * SEG;
+  constexpr int BLK = kBackBlock * kTriVbStride + 16;  // doubles of one staged block
+  __shared__ __align__(16) double buf[2][BLK];
   const int f = list[blockIdx.x];
   const FragInfo fi = frag[f];
   const int n = fi.nbf;
   const TriWs W = tri_ws(ws_eig, max_n, n);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = kTriRowsPerWave * wave + lane / kTriLanes, seg = lane % kTriLanes;
+  const int lane = threadIdx.x;
+  const int row = kTriRowsPerWave * blockIdx.y + lane / kTriLanes, seg = lane % kTriLanes;
+  if (kTriRowsPerWave * blockIdx.y >= n) return;
   const bool has_row = row < n;
-  const int nrefl = n > 2 ? refl_off(n - 2, n) : 0;
-  for (int i = threadIdx.x; i < nrefl; i += kTriThreads) sm[i] = W.refl[i];
   // z[c]: component 2 c + seg of eigenvector `row` of T
   double z[SEG];
 #pragma unroll
@@ -561,49 +624,37 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
 #pragma unroll
     for (int c = 0; c < SEG; ++c) z[c] = zr[kTriLanes * c];
   }
-  __syncthreads();
-  // Block b holds reflectors r_i = k0 - i, i < kBackBlock, k0 = n - 3 -
-  // kBackBlock b, applied in the order r_0, r_1, ... (H_{r_0} first); a
-  // reflector index below 0 is a zero vector with tau = 0.  The helper
-  // wave expands block b + 1 (zeros outside r_i + 1 .. n - 1) and its Gram
-  // entries g_ij = v_i . v_j into the buffers of its parity one step ahead.
-  const int nb = n >= 3 ? (n - 2 + kBackBlock - 1) / kBackBlock : 0;
-  auto expand = [&](int b) {
-    const int k0 = n - 3 - kBackBlock * b;
-    double* dst = &vbuf[b & 1][0][0];
-    double* g = gbuf[b & 1];
-#pragma unroll
-    for (int i = 0; i < kBackBlock; ++i) {
-      const int k = k0 - i;
-      const double* vk = sm + (k >= 0 ? refl_off(k, n) - (k + 1) : 0);
-      for (int j = lane; j < NC; j += 64)
-        dst[i * NC + j] = (k >= 0 && j > k && j < n) ? vk[j] : 0.0;
-    }
-    // the expansion above is this wave's own LDS writes: in order for its
-    // reads below
-#pragma unroll
-    for (int i = 1; i < kBackBlock; ++i)
-#pragma unroll
-      for (int jj = 0; jj < i; ++jj) {
-        double d = 0.0;
-        for (int j = lane; j < NC; j += 64) d = fma(dst[i * NC + j], dst[jj * NC + j], d);
-        d = wave_sum_dpp(d);
-        if (lane == 0) g[i * kBackBlock + jj] = d;
-      }
-    if (lane < kBackBlock) {
-      const int k = k0 - lane;
-      g[lane * kBackBlock + lane] = k >= 0 ? W.tau[k] : 0.0;
-    }
+  const int nb = back_blocks(n);
+  // block b's vectors and Gram entries into buf[b & 1] (whole-wave copies)
+  auto stage = [&](int b) __attribute__((always_inline)) {
+    const double* v = W.VB + (size_t)b * kBackBlock * kTriVbStride;
+    const double* g = W.GB + (size_t)b * 16;
+    double* d = buf[b & 1];
+    for (int e = lane; e < kBackBlock * kTriVbStride; e += 64) d[e] = v[e];
+    if (lane < 16) d[kBackBlock * kTriVbStride + lane] = g[lane];
   };
-  if (wave == kTriHelper && nb > 0) expand(0);
+  if (nb > 0) stage(0);
   __syncthreads();
   for (int b = 0; b < nb; ++b) {
-    if (wave == kTriHelper && b + 1 < nb) expand(b + 1);
+    // the next block's loads are issued first; their LDS writes land after
+    // this block's reads (the barrier below)
+    double nxt[(kBackBlock * kTriVbStride + 63) / 64];
+    double gn = 0.0;
+    const bool more = b + 1 < nb;
+    if (more) {
+      const double* v = W.VB + (size_t)(b + 1) * kBackBlock * kTriVbStride;
+#pragma unroll
+      for (int u = 0; u < (kBackBlock * kTriVbStride + 63) / 64; ++u) {
+        const int e = lane + 64 * u;
+        nxt[u] = e < kBackBlock * kTriVbStride ? v[e] : 0.0;
+      }
+      if (lane < 16) gn = W.GB[(size_t)(b + 1) * 16 + lane];
+    }
     const int kmin = n - 3 - kBackBlock * b - (kBackBlock - 1);  // every v_i vanishes on <= kmin
-    const double* v = &vbuf[b & 1][0][0];
-    const double* g = gbuf[b & 1];
+    const double* v = buf[b & 1];
+    const double* g = v + kBackBlock * kTriVbStride;
     // w_i = v_i . z; groups of kChunk components entirely at or below kmin
-    // are skipped (a test uniform over the workgroup)
+    // are skipped (a test uniform over the wave)
     double w[kBackBlock];
 #pragma unroll
     for (int i = 0; i < kBackBlock; ++i) w[i] = 0.0;
@@ -614,7 +665,7 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
         for (int u = 0; u < kChunk; ++u) {
           const int c = kChunk * q + u, j = kTriLanes * c + seg;
 #pragma unroll
-          for (int i = 0; i < kBackBlock; ++i) w[i] = fma(v[i * NC + j], z[c], w[i]);
+          for (int i = 0; i < kBackBlock; ++i) w[i] = fma(v[i * kTriVbStride + j], z[c], w[i]);
         }
     // y_i = tau_i (w_i - sum_{j < i} g_ij y_j): H_{r_0} first, then H_{r_1}, ...
     double y[kBackBlock];
@@ -625,8 +676,6 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
       for (int jj = 0; jj < i; ++jj) a -= g[i * kBackBlock + jj] * y[jj];
       y[i] = g[i * kBackBlock + i] * a;
     }
-    // read v again rather than keep its values live next to z
-    asm volatile("" ::: "memory");
 #pragma unroll
     for (int q = 0; q < SEG / kChunk; ++q)
       if (kTriLanes * kChunk * (q + 1) - 1 > kmin)
@@ -635,9 +684,19 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
           const int c = kChunk * q + u, j = kTriLanes * c + seg;
           double zc = z[c];
 #pragma unroll
-          for (int i = 0; i < kBackBlock; ++i) zc -= y[i] * v[i * NC + j];
+          for (int i = 0; i < kBackBlock; ++i) zc -= y[i] * v[i * kTriVbStride + j];
           z[c] = zc;
         }
+    __syncthreads();
+    if (more) {
+      double* d = buf[(b + 1) & 1];
+#pragma unroll
+      for (int u = 0; u < (kBackBlock * kTriVbStride + 63) / 64; ++u) {
+        const int e = lane + 64 * u;
+        if (e < kBackBlock * kTriVbStride) d[e] = nxt[u];
+      }
+      if (lane < 16) d[kBackBlock * kTriVbStride + lane] = gn;
+    }
     __syncthreads();
   }
   // C column `row` (ascending eigenvalue order)
@@ -648,31 +707,32 @@ __global__ __launch_bounds__(kTriThreads) void eigh_tri_back_kernel(
       if (i < n) C[fi.off_C + (size_t)i * n + row] = z[c];
     }
   }
-  // occupied columns into LDS (the reflectors are no longer needed), then
-  // D = C_occ C_occ^T and max |D - D_old|
-  const int nocc = fi.nocc;
-  double* Co = sm;  // [nocc][n]
-  if (has_row && row < nocc) {
-#pragma unroll
-    for (int c = 0; c < SEG; ++c) {
-      const int i = opaque(seg) + kTriLanes * c;
-      if (i < n) Co[row * n + i] = z[c];
-    }
-  }
-  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void eigh_tri_density_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ list,
+    const double* __restrict__ Dold, const double* __restrict__ C,
+    const double* __restrict__ eps, double* __restrict__ Dnew, double* __restrict__ dD_max,
+    int32_t* __restrict__ flags) {
+  __shared__ double red[4];
+  const FragInfo fi = frag[list[blockIdx.x]];
+  const int n = fi.nbf, nocc = fi.nocc;
+  const double* Cf = C + fi.off_C;
   double dmax = 0.0;
-  for (int e = threadIdx.x; e < n * n; e += kTriThreads) {
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e < n * n) {
     const int l = e / n, s = e - (e / n) * n;
     double acc = 0.0;
-    for (int k = 0; k < nocc; ++k) acc = fma(Co[k * n + l], Co[k * n + s], acc);
+    for (int k = 0; k < nocc; ++k) acc = fma(Cf[(size_t)l * n + k], Cf[(size_t)s * n + k], acc);
     Dnew[fi.off_C + e] = acc;
-    dmax = fmax(dmax, fabs(acc - Dold[fi.off_C + e]));
+    dmax = fabs(acc - Dold[fi.off_C + e]);
   }
   dmax = block_max(dmax, red);
   if (threadIdx.x == 0) {
     atomic_max_nonneg(dD_max, dmax);
     const double* ev = eps + fi.off_eps;
-    if (nocc > 0 && nocc < n && !(ev[nocc] > ev[nocc - 1])) atomicOr(flags, FEF_FLAG_GAP);
+    if (blockIdx.y == 0 && nocc > 0 && nocc < n && !(ev[nocc] > ev[nocc - 1]))
+      atomicOr(flags, FEF_FLAG_GAP);
   }
 }
 
@@ -681,12 +741,6 @@ hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* D
                            double* ws_eig, hipStream_t st) {
   const int nmax = p.eig_large_max_nbf;
   if (nmax > kTriMax) return hipErrorInvalidValue;
-  int omax = 0;
-  for (int32_t f : p.eig_large) omax = std::max(omax, p.frag[f].nocc);
-  // back kernel: the packed reflectors, later the occupied block
-  const size_t lds_back =
-      std::max<size_t>((size_t)refl_off(std::max(nmax - 2, 0), nmax), (size_t)omax * nmax) *
-      sizeof(double);
   const size_t lds_bis = 3 * (size_t)nmax * sizeof(double);
   const size_t lds_vec = vec_lds_bytes(nmax);
   if (lds_vec > 150 * 1024) return hipErrorInvalidValue;
@@ -699,28 +753,27 @@ hipError_t launch_eigh_tri(const fef_plan_s& p, const double* F, const double* D
       configured = true;
     }
   }
-  if (lds_back > 140 * 1024) return hipErrorInvalidValue;
   const dim3 grid((unsigned)p.eig_large.size());
   const dim3 grid_bis(grid.x, (unsigned)((nmax + kBisPer - 1) / kBisPer));
   const dim3 grid_vec(grid.x, (unsigned)((nmax + kVecThreads - 1) / kVecThreads));
+  const int nbmax = nmax >= 3 ? (nmax - 2 + kBackBlock - 1) / kBackBlock : 0;
+  const dim3 grid_exp(grid.x, (unsigned)std::max(nbmax, 1));
+  const dim3 grid_back(grid.x, (unsigned)((nmax + kTriRowsPerWave - 1) / kTriRowsPerWave));
+  const dim3 grid_den(grid.x, (unsigned)((nmax * nmax + 255) / 256));
 #define FEF_TRI(S)                                                                             \
   {                                                                                            \
-    static bool configured = false;                                                            \
-    if (!configured) {                                                                         \
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&eigh_tri_back_kernel<S>),       \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 140 * 1024);       \
-      (void)hipGetLastError();                                                                 \
-      configured = true;                                                                       \
-    }                                                                                          \
     hipLaunchKernelGGL(eigh_tri_reduce_kernel<S>, grid, dim3(kTriThreads), 0, st, p.d_frag,    \
                        p.d_eig_large, F, ws_eig, nmax);                                        \
     hipLaunchKernelGGL(eigh_tri_bisect_kernel, grid_bis, dim3(kBisThreads), lds_bis, st,       \
                        p.d_frag, p.d_eig_large, eps, ws_eig, nmax);                            \
     hipLaunchKernelGGL(eigh_tri_vectors_kernel, grid_vec, dim3(64), lds_vec, st, p.d_frag,     \
                        p.d_eig_large, eps, ws_eig, nmax);                                      \
-    hipLaunchKernelGGL(eigh_tri_back_kernel<S>, grid, dim3(kTriThreads), lds_back, st,        \
-                       p.d_frag, p.d_eig_large, Dold, C, eps, Dnew, dD_max, flags, ws_eig,     \
-                       nmax);                                                                  \
+    hipLaunchKernelGGL(eigh_tri_expand_kernel<S>, grid_exp, dim3(64), 0, st, p.d_frag,         \
+                       p.d_eig_large, ws_eig, nmax);                                           \
+    hipLaunchKernelGGL(eigh_tri_back_kernel<S>, grid_back, dim3(64), 0, st, p.d_frag,          \
+                       p.d_eig_large, C, ws_eig, nmax);                                        \
+    hipLaunchKernelGGL(eigh_tri_density_kernel, grid_den, dim3(256), 0, st, p.d_frag,          \
+                       p.d_eig_large, Dold, C, eps, Dnew, dD_max, flags);                      \
   }
   if (nmax <= 96) FEF_TRI(48) else FEF_TRI(76)
 #undef FEF_TRI
