@@ -128,7 +128,10 @@ typedef enum {
   FEF_Q_SURR_WS_BYTES = 16, /* workspace of fef_coupling_modes and
                                fef_fragment_invariants                  */
   FEF_Q_BPACK_ELEMS = 17,   /* doubles in the packed coefficient pool    */
-  FEF_Q_COUPLED_WS_BYTES = 18 /* workspace of fef_coupled_pair_energies  */
+  FEF_Q_COUPLED_WS_BYTES = 18, /* workspace of fef_coupled_pair_energies */
+  FEF_Q_DRESSING_WS_BYTES = 19, /* workspace of fef_dimer_dressing        */
+  FEF_Q_HOO_ELEMS = 20,     /* doubles in the Hoo pool (nocc^2 per fragment) */
+  FEF_Q_HVV_ELEMS = 21      /* doubles in the Hvv pool (nvir^2 per fragment) */
 } fef_query;
 
 /* `prec` matters for FEF_Q_OPS_BYTES, FEF_Q_HALF_WS_BYTES,
@@ -331,7 +334,8 @@ fef_status fef_pair_energies_noalloc(fef_plan plan, const void* ops, const doubl
  *   B, C, eps, G : input pools (device), as for fef_half_transform and
  *                  fef_pair_energies.
  *   tol, maxit   : stopping rule (tol >= 0 finite, maxit >= 0; maxit = 0
- *                  gives the uncoupled energy of fef_pair_energies).
+ *                  gives the uncoupled energy of fef_pair_energies without
+ *                  forming W, and sets flag bit 2).
  *   E2_pair      : [npair] out, in the caller's pair order (device).
  *   E2_total     : [1] out, FP64 sum over pairs in a fixed order (device).
  *   iters        : optional [npair] int32 out, CG iterations per pair.
@@ -345,6 +349,28 @@ fef_status fef_coupled_pair_energies(fef_plan plan, const double* B, const doubl
                                      int32_t maxit, double* E2_pair, double* E2_total,
                                      int32_t* iters, int32_t* flags, void* ws, size_t ws_bytes,
                                      void* stream);
+
+/* Cross-fragment dressing of every fragment's one-body intermediates by the
+ * dimer doubles (Sec. III, Eqs. MPij and MPab, their dimer-doubles terms;
+ * the fragment singles vanish at this order, so Eq. MPia adds nothing):
+ *     Hoo^x[i][i1] =  2 sum_y sum_{a, j, b} (ia|jb) t[i1 a, j b]
+ *     Hvv^x[a][a1] = -2 sum_y sum_{i, j, b} (i a1|jb) t[i a, j b]
+ * over every pair (x, y) of the list (the factor 2 sums the spin of the
+ * other fragment's orbitals; no exchange between fragments), each pair
+ * dressing both of its fragments.  t are the dimer doubles of
+ * fef_coupled_pair_energies with the same tol and maxit: maxit = 0 gives
+ * t = -(ia|jb) / D, the amplitudes of fef_pair_energies.
+ *   B, C, eps, G : input pools (device).
+ *   E2_pair, E2_total : as fef_coupled_pair_energies.
+ *   Hoo : out pool, [nocc][nocc] per fragment (FEF_Q_HOO_ELEMS doubles).
+ *   Hvv : out pool, [nvir][nvir] per fragment (FEF_Q_HVV_ELEMS doubles).
+ *   ws  : FEF_Q_DRESSING_WS_BYTES bytes (device).
+ * Each fragment's blocks are summed over its pairs in pair order, so the
+ * result is bitwise reproducible for a given plan. */
+fef_status fef_dimer_dressing(fef_plan plan, const double* B, const double* C, const double* eps,
+                              const double* G, double tol, int32_t maxit, double* E2_pair,
+                              double* E2_total, double* Hoo, double* Hvv, int32_t* flags,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Distant-pair surrogate.  A project addition: the paper has no learned

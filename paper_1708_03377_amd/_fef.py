@@ -32,6 +32,7 @@ Q_OPS_BYTES, Q_HALF_WS_BYTES, Q_PAIR_WS_BYTES, Q_FIELD_WS_BYTES, Q_SCF_WS_BYTES 
 Q_BOV_ELEMS, Q_W_ELEMS, Q_NITEMS, Q_B_ELEMS, Q_C_ELEMS, Q_EPS_ELEMS, Q_G_ELEMS, Q_NPAIR = range(5, 13)
 Q_NSLOT, Q_NENTRIES, Q_MASKED_WS_BYTES, Q_SURR_WS_BYTES, Q_BPACK_ELEMS = 13, 14, 15, 16, 17
 Q_COUPLED_WS_BYTES = 18
+Q_DRESSING_WS_BYTES, Q_HOO_ELEMS, Q_HVV_ELEMS = 19, 20, 21
 
 MLP_NIN, MLP_NHID, MLP_NPARAM, MLP_STRIDE, MLP_NSTATS = 17, 128, 18945, 18952, 36
 
@@ -45,7 +46,8 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_mlp_pack", "fef_mlp_forward", "fef_mlp_train_step",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
                 "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_plan_stage_timing",
-                "fef_plan_stage_ms", "fef_coupled_pair_energies", "fef_status_string")
+                "fef_plan_stage_ms", "fef_coupled_pair_energies", "fef_dimer_dressing",
+                "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -115,6 +117,8 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_pair_energies_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.fef_coupled_pair_energies.argtypes = [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp,
                                               sz, vp]
+    lib.fef_dimer_dressing.argtypes = [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp, vp, sz,
+                                       vp]
     lib.fef_plan_stage_timing.argtypes = [vp, i32]
     lib.fef_plan_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fef_status_string.argtypes = [i32]
@@ -245,6 +249,14 @@ def fef_coupled_pair_energies(plan, B, C, eps, G, tol, maxit, E2_pair, E2_total,
     _check("fef_coupled_pair_energies", load_library().fef_coupled_pair_energies(
         plan.handle, _ptr(B), _ptr(C), _ptr(eps), _ptr(G), float(tol), int(maxit), _ptr(E2_pair),
         _ptr(E2_total), _ptr(iters), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_dimer_dressing(plan, B, C, eps, G, tol, maxit, E2_pair, E2_total, Hoo, Hvv, flags, ws,
+                       stream=None):
+    _check("fef_dimer_dressing", load_library().fef_dimer_dressing(
+        plan.handle, _ptr(B), _ptr(C), _ptr(eps), _ptr(G), float(tol), int(maxit), _ptr(E2_pair),
+        _ptr(E2_total), _ptr(Hoo), _ptr(Hvv), _ptr(flags), _ptr(ws), _nbytes(ws),
+        _stream(stream)))
 
 
 def fef_coulomb_field(plan, B, G, D, J, ws, stream=None):

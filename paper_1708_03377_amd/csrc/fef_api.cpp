@@ -29,7 +29,8 @@ void free_plan(fef_plan_s* p) {
                   p->d_off_G, p->d_naux_cls_off,
                   p->d_nbr_ptr, p->d_nbr_idx, p->d_nbr_s, p->d_eig_small,
                   p->d_eig_mid, p->d_eig_large, p->d_gfrag, p->d_glist, p->d_off_Bp,
-                  p->d_off_tri, p->d_chunk_C, p->d_chunk_Bp, p->d_cp_list};
+                  p->d_off_tri, p->d_chunk_C, p->d_chunk_Bp, p->d_cp_list, p->d_rec_off,
+                  p->d_off_oo, p->d_off_vv, p->d_inc_ptr, p->d_inc_base};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t& e : p->stage_ev)
@@ -310,10 +311,7 @@ fef_status fef_plan_create(const fef_system_desc* d, fef_plan* out) {
     e = upload(&p->d_gfrag, std::vector<FragInfo>{g});
   }
   if (e == hipSuccess) e = upload(&p->d_glist, std::vector<int32_t>{0});
-  if (e == hipSuccess) {
-    coupled_setup(*p);
-    e = upload(&p->d_cp_list, p->cp_list);
-  }
+  if (e == hipSuccess) e = coupled_setup(*p);
   if (e == hipSuccess) {
     // nfrag + 1 entries: the last is the pool size
     std::vector<int64_t> offp(d->nfrag + 1, 0);
@@ -398,6 +396,9 @@ fef_status fef_plan_query(fef_plan p, fef_query what, fef_prec prec, int64_t* ou
     case FEF_Q_SURR_WS_BYTES: *out = surr_ws_bytes(*p); break;
     case FEF_Q_BPACK_ELEMS: *out = p->nBp; break;
     case FEF_Q_COUPLED_WS_BYTES: *out = coupled_ws_bytes(*p); break;
+    case FEF_Q_DRESSING_WS_BYTES: *out = dressing_ws_bytes(*p); break;
+    case FEF_Q_HOO_ELEMS: *out = p->n_oo; break;
+    case FEF_Q_HVV_ELEMS: *out = p->n_vv; break;
     default: return FEF_E_ARG;
   }
   return FEF_OK;

@@ -139,6 +139,7 @@ namespace fef {
 struct CgSlot {
   int64_t v, d, t, r, p, ap, q, ph, hp, hh, size;
   int64_t nmax;  // largest amplitude count ov_x ov_y of the group
+  int64_t npb;   // doubles of p's storage (at least one per thread: partial sums)
 };
 // Pairs of one class of x (a list range), solved by nslots workgroups; lds:
 // the search direction and its product live in LDS.
@@ -220,6 +221,14 @@ struct fef_plan_s {
   std::vector<fef::CoupledGroup> cp_groups;
   std::vector<int32_t> cp_list;
   int32_t* d_cp_list = nullptr;
+  // dimer dressings: per-pair record offsets, per-fragment output offsets,
+  // and each fragment's record parts in pair order
+  int64_t n_rec = 0, n_oo = 0, n_vv = 0;
+  int64_t* d_rec_off = nullptr;
+  int64_t* d_off_oo = nullptr;
+  int64_t* d_off_vv = nullptr;
+  int32_t* d_inc_ptr = nullptr;
+  int64_t* d_inc_base = nullptr;
 };
 
 namespace fef {
@@ -330,9 +339,11 @@ inline void stage_mark(const fef_plan_s& p, int i, hipStream_t st) {
 
 // Compute units of the current device (queried once, cached).
 int compute_units();
-// coupled dimer doubles: pair groups (plan creation) and workspace bytes
-void coupled_setup(fef_plan_s& p);
+// coupled dimer doubles and dressings: pair groups and tables (plan
+// creation; allocates), workspace bytes
+hipError_t coupled_setup(fef_plan_s& p);
 int64_t coupled_ws_bytes(const fef_plan_s& p);
+int64_t dressing_ws_bytes(const fef_plan_s& p);
 
 // One-time kernel attributes (dynamic LDS above 64 KB).
 

@@ -375,7 +375,8 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
     const int32_t* __restrict__ list, int32_t count, const double* __restrict__ X,
     const double* __restrict__ Y, int P0, const double* __restrict__ eps,
     double* __restrict__ slots, CgSlot L, double tol, int maxit, double* __restrict__ E2_pair,
-    int32_t* __restrict__ iters, int32_t* __restrict__ flags) {
+    int32_t* __restrict__ iters, int32_t* __restrict__ flags, double* __restrict__ rec,
+    const int64_t* __restrict__ rec_off) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ double red[kCgWaves];
   __shared__ double red2[2][kCgWaves];
@@ -395,8 +396,8 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
   int* tab;
   if constexpr (kLds) {
     pb = reinterpret_cast<double*>(lds_raw);
-    apb = pb + L.nmax;
-    tab = reinterpret_cast<int*>(lds_raw + 16 * L.nmax);
+    apb = pb + L.npb;
+    tab = reinterpret_cast<int*>(apb + L.nmax + kCgThreads);  // after the partial-sum room
   } else {
     pb = slot + L.p;
     apb = slot + L.ap;
@@ -413,6 +414,10 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       if (tid == 0) {
         E2_pair[k] = 0.0;
         if (iters) iters[k] = 0;
+      }
+      if (rec) {
+        const int nr = ox * ox + vx * vx + oy * oy + vy * vy;
+        for (int u = tid; u < nr; u += kCgThreads) rec[rec_off[k] + u] = 0.0;
       }
       continue;
     }
@@ -456,8 +461,8 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       const int i = ij / oy, j = ij - (ij / oy) * oy;
       D[e] = (ex[ox + a] - ex[i]) + (ey[oy + b] - ey[j]);
     }
-    // operator blocks
-    {
+    // operator blocks (not needed for maxit = 0: t = -v / D)
+    if (maxit > 0) {
       const int KS = tile_ks(nV);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, ox, ox}, vx, vx, KronSide{Yy, nny, fy.nbf, oy, oy}, vy,
                 vy, P0, s, wave, lane,
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
                 });
       zero_tile_pad(Aq, nV);
     }
-    {
+    if (maxit > 0) {
       const int KS = tile_ks(nPH);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, ox, ox}, vx, vx, KronSide{Yy, nny, fy.nbf, 0, 0}, oy,
                 oy, P0, s, wave, lane,
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
                 });
       zero_tile_pad(Aph, nPH);
     }
-    {
+    if (maxit > 0) {
       const int KS = tile_ks(nHP);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, 0, 0}, ox, ox, KronSide{Yy, nny, fy.nbf, oy, oy}, vy,
                 vy, P0, s, wave, lane,
@@ -484,7 +489,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
                 });
       zero_tile_pad(Ahp, nHP);
     }
-    {
+    if (maxit > 0) {
       const int KS = tile_ks(nO);
       kron_gemm(KronSide{Xx, nnx, fx.nbf, 0, 0}, ox, ox, KronSide{Yy, nny, fy.nbf, 0, 0}, oy,
                 oy, P0, s, wave, lane,
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
     // start: t = b / D with b = -v; r = b - (D + W) t; p = z = r / D.
     // Conjugate gradients as the oracle takes them; t, r and D live in the
     // slot, p and W p in LDS when they fit.
-    double nb, rr, vt = 0.0;
+    double nb = 0.0, rr = 0.0, vt = 0.0;
     int it = 0;
     double bb = 0.0;
 #pragma unroll 4
@@ -520,61 +525,169 @@ __global__ __launch_bounds__(kCgThreads) void coupled_cg_kernel(
       t[e] = t0;
       pb[e] = t0;
       bb = fma(b, b, bb);
+      if (maxit == 0) vt = fma(v[e], t0, vt);
     }
     nb = sqrt(block_sum(bb, red));
-    apply();
-    double rz = 0.0;
-    rr = 0.0;
-#pragma unroll 4
-    for (int e = tid; e < n; e += kCgThreads) {
-      const double re = -v[e] - fma(D[e], pb[e], apb[e]);
-      const double z = re / D[e];
-      r[e] = re;
-      pb[e] = z;
-      rz = fma(re, z, rz);
-      rr = fma(re, re, rr);
-    }
-    block_sum_pair(rz, rr, red2);
-    while (it < maxit && !(sqrt(rr) <= tol * nb)) {
+    if (maxit > 0) {
       apply();
-      double pap = 0.0;
-#pragma unroll 4
-      for (int e = tid; e < n; e += kCgThreads) {
-        const double pe = pb[e];
-        pap = fma(pe, fma(D[e], pe, apb[e]), pap);
-      }
-      pap = block_sum(pap, red);
-      const double alpha = rz / pap;
-      double rzn = 0.0;
+      double rz = 0.0;
       rr = 0.0;
 #pragma unroll 4
       for (int e = tid; e < n; e += kCgThreads) {
-        const double pe = pb[e];
-        t[e] = fma(alpha, pe, t[e]);
-        const double re = fma(-alpha, fma(D[e], pe, apb[e]), r[e]);
-        r[e] = re;
+        const double re = -v[e] - fma(D[e], pb[e], apb[e]);
         const double z = re / D[e];
-        rzn = fma(re, z, rzn);
+        r[e] = re;
+        pb[e] = z;
+        rz = fma(re, z, rz);
         rr = fma(re, re, rr);
       }
-      block_sum_pair(rzn, rr, red2);
-      const double beta = rzn / rz;
+      block_sum_pair(rz, rr, red2);
+      while (it < maxit && !(sqrt(rr) <= tol * nb)) {
+        apply();
+        double pap = 0.0;
 #pragma unroll 4
-      for (int e = tid; e < n; e += kCgThreads) pb[e] = fma(beta, pb[e], r[e] / D[e]);
-      rz = rzn;
-      ++it;
-      __syncthreads();
+        for (int e = tid; e < n; e += kCgThreads) {
+          const double pe = pb[e];
+          pap = fma(pe, fma(D[e], pe, apb[e]), pap);
+        }
+        pap = block_sum(pap, red);
+        const double alpha = rz / pap;
+        double rzn = 0.0;
+        rr = 0.0;
+#pragma unroll 4
+        for (int e = tid; e < n; e += kCgThreads) {
+          const double pe = pb[e];
+          t[e] = fma(alpha, pe, t[e]);
+          const double re = fma(-alpha, fma(D[e], pe, apb[e]), r[e]);
+          r[e] = re;
+          const double z = re / D[e];
+          rzn = fma(re, z, rzn);
+          rr = fma(re, re, rr);
+        }
+        block_sum_pair(rzn, rr, red2);
+        const double beta = rzn / rz;
+#pragma unroll 4
+        for (int e = tid; e < n; e += kCgThreads) pb[e] = fma(beta, pb[e], r[e] / D[e]);
+        rz = rzn;
+        ++it;
+        __syncthreads();
+      }
+#pragma unroll 4
+      for (int e = tid; e < n; e += kCgThreads) vt = fma(v[e], t[e], vt);
     }
-#pragma unroll 4
-    for (int e = tid; e < n; e += kCgThreads) vt = fma(v[e], t[e], vt);
     const double E = 4.0 * block_sum(vt, red);
     if (tid == 0) {
       E2_pair[k] = E;
       if (iters) iters[k] = it;
       if (!isfinite(E)) atomicOr(flags, FEF_FLAG_NONFINITE);
-      if (!(sqrt(rr) <= tol * nb)) atomicOr(flags, FEF_FLAG_NOCONV);
+      // maxit = 0 stops at the start, the residual of t = -v / D unformed
+      if (maxit == 0 || !(sqrt(rr) <= tol * nb)) atomicOr(flags, FEF_FLAG_NOCONV);
+    }
+    if (rec) {
+      // the pair's one-body dressings (Eqs. MPij, MPab, doubles terms) into
+      // its record [Hoo^x][Hvv^x][Hoo^y][Hvv^y]; p's storage, free after the
+      // solve, holds the partial sums of short outputs
+      double* R = rec + rec_off[k];
+      double* scratch = pb;
+      const double* vd = v;
+      const double* td = t;
+      if constexpr (kLds) {
+        // v and t into LDS (p and W p are free after the solve), partial
+        // sums in the room behind them
+        __syncthreads();
+        for (int e = tid; e < n; e += kCgThreads) {
+          pb[e] = v[e];
+          apb[e] = t[e];
+        }
+        vd = pb;
+        td = apb;
+        scratch = apb + L.nmax;
+      }
+      const int64_t vyn = (int64_t)vy * nO;
+      // nout outputs, each sum over kk < K of term(o, kk), times scale:
+      // outputs fewer than the threads are split over parts summed in order
+      auto split_sum = [&](int nout, int K, double scale, double* dst, auto term)
+                           __attribute__((always_inline)) {
+        if (nout >= kCgThreads) {
+          for (int o = tid; o < nout; o += kCgThreads) {
+            double acc = 0.0;
+            for (int kk = 0; kk < K; ++kk) acc += term(o, kk);
+            dst[o] = scale * acc;
+          }
+          return;
+        }
+        const int np = kCgThreads / nout;
+        if (tid < np * nout) {
+          const int o = tid % nout, part = tid / nout;
+          double acc = 0.0;
+          for (int kk = part; kk < K; kk += np) acc += term(o, kk);
+          scratch[part * nout + o] = acc;
+        }
+        __syncthreads();
+        for (int o = tid; o < nout; o += kCgThreads) {
+          double acc = 0.0;
+          for (int part = 0; part < np; ++part) acc += scratch[part * nout + o];
+          dst[o] = scale * acc;
+        }
+        __syncthreads();
+      };
+      __syncthreads();
+      // Hoo^x[i][i1] = 2 sum_{a b, j} v[a b, i, j] t[a b, i1, j]
+      split_sum(ox * ox, nV, 2.0, R, [&](int o, int ab) __attribute__((always_inline)) {
+        const int i = o / ox, i1 = o - (o / ox) * ox;
+        const double* vr = vd + (int64_t)ab * nO + i * oy;
+        const double* tr = td + (int64_t)ab * nO + i1 * oy;
+        double q = 0.0;
+        for (int j = 0; j < oy; ++j) q = fma(vr[j], tr[j], q);
+        return q;
+      });
+      // Hvv^x[a][a1] = -2 sum_{b, i j} v[a1 b, i j] t[a b, i j]
+      split_sum(vx * vx, (int)vyn, -2.0, R + ox * ox,
+                [&](int o, int m) __attribute__((always_inline)) {
+                  const int a = o / vx, a1 = o - (o / vx) * vx;
+                  return vd[a1 * vyn + m] * td[a * vyn + m];
+                });
+      // Hoo^y[j][j1] = 2 sum_{a b, i} v[a b, i, j] t[a b, i, j1]
+      split_sum(oy * oy, nV, 2.0, R + ox * ox + vx * vx,
+                [&](int o, int ab) __attribute__((always_inline)) {
+                  const int j = o / oy, j1 = o - (o / oy) * oy;
+                  const double* vr = vd + (int64_t)ab * nO + j;
+                  const double* tr = td + (int64_t)ab * nO + j1;
+                  double q = 0.0;
+                  for (int i = 0; i < ox; ++i) q = fma(vr[i * oy], tr[i * oy], q);
+                  return q;
+                });
+      // Hvv^y[b][b1] = -2 sum_{a, i j} v[a b1, i j] t[a b, i j]
+      split_sum(vy * vy, vx, -2.0, R + ox * ox + vx * vx + oy * oy,
+                [&](int o, int a) __attribute__((always_inline)) {
+                  const int b = o / vy, b1 = o - (o / vy) * vy;
+                  const double* vr = vd + (int64_t)(a * vy + b1) * nO;
+                  const double* tr = td + (int64_t)(a * vy + b) * nO;
+                  double q = 0.0;
+                  for (int ij = 0; ij < nO; ++ij) q = fma(vr[ij], tr[ij], q);
+                  return q;
+                });
     }
     __syncthreads();
+  }
+}
+
+// Per-fragment dressings: the sum, in pair order, of the fragment's parts of
+// the records of its pairs (inc_base: where each part starts).
+__global__ __launch_bounds__(256) void dressing_reduce_kernel(
+    const FragInfo* __restrict__ frag, const int32_t* __restrict__ inc_ptr,
+    const int64_t* __restrict__ inc_base, const int64_t* __restrict__ off_oo,
+    const int64_t* __restrict__ off_vv, const double* __restrict__ rec, double* __restrict__ Hoo,
+    double* __restrict__ Hvv) {
+  const int f = blockIdx.x;
+  const FragInfo fi = frag[f];
+  const int noo = fi.nocc * fi.nocc, nvv = fi.nvir * fi.nvir;
+  const int b0 = inc_ptr[f], b1 = inc_ptr[f + 1];
+  for (int e = blockIdx.y * 256 + threadIdx.x; e < noo + nvv; e += 256 * gridDim.y) {
+    double acc = 0.0;
+    for (int m = b0; m < b1; ++m) acc += rec[inc_base[m] + e];
+    if (e < noo) Hoo[off_oo[f] + e] = acc;
+    else Hvv[off_vv[f] + (e - noo)] = acc;
   }
 }
 
@@ -592,9 +705,20 @@ __global__ __launch_bounds__(256) void coupled_total_kernel(const double* __rest
 
 }  // namespace
 
+template <typename T>
+static hipError_t upload_vec(T** dst, const std::vector<T>& src) {
+  *dst = nullptr;
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
 // Pair groups by the class of x: one launch each, slots sized for the
-// group's largest pair.
-void coupled_setup(fef_plan_s& p) {
+// group's largest pair.  Dressing tables: each pair's record [Hoo^x][Hvv^x]
+// [Hoo^y][Hvv^y] (oriented x, y), the output offsets of every fragment, and
+// each fragment's record parts in pair order.
+hipError_t coupled_setup(fef_plan_s& p) {
   p.cp_groups.clear();
   p.cp_list.clear();
   const int ncu = compute_units();
@@ -624,18 +748,20 @@ void coupled_setup(fef_plan_s& p) {
       p.cp_list.push_back(k);
     }
     const int64_t tab_bytes = 8 * (nV + nO + nPH + nHP);
-    const int64_t lds_bytes = 16 * nmax + tab_bytes;
+    const int64_t npb = std::max<int64_t>(nmax, kCgThreads);
+    const int64_t lds_bytes = 8 * (npb + nmax + kCgThreads) + tab_bytes;
     g.lds = lds_bytes <= kCgLdsMax - 1024;
     g.lds_bytes = (size_t)(g.lds ? lds_bytes : tab_bytes);
     auto al = [](int64_t x) { return round_up(std::max<int64_t>(x, 1), 64); };
     CgSlot& L = g.L;
     int64_t o = 0;
     L.nmax = nmax;
+    L.npb = npb;
     L.v = o; o += al(nmax);
     L.d = o; o += al(nmax);
     L.t = o; o += al(nmax);
     L.r = o; o += al(nmax);
-    L.p = o; o += g.lds ? 0 : al(nmax);
+    L.p = o; o += g.lds ? 0 : al(npb);
     L.ap = o; o += g.lds ? 0 : al(nmax);
     L.q = o; o += al(tiled_doubles(nV));
     L.ph = o; o += al(tiled_doubles(nPH));
@@ -648,6 +774,46 @@ void coupled_setup(fef_plan_s& p) {
     g.nslots = (int32_t)ns;
     p.cp_groups.push_back(g);
   }
+  std::vector<int64_t> rec_off(std::max<int64_t>(p.npair, 1), 0), off_oo(p.nfrag), off_vv(p.nfrag);
+  std::vector<std::vector<std::pair<int32_t, int64_t>>> parts(p.nfrag);
+  int64_t o = 0;
+  for (int64_t k = 0; k < p.npair; ++k) {
+    const FragInfo& fx = p.frag[p.pairs[k].x];
+    const FragInfo& fy = p.frag[p.pairs[k].y];
+    rec_off[k] = o;
+    const int64_t xpart = (int64_t)fx.nocc * fx.nocc + (int64_t)fx.nvir * fx.nvir;
+    parts[p.pairs[k].x].push_back({(int32_t)k, o});
+    parts[p.pairs[k].y].push_back({(int32_t)k, o + xpart});
+    o += xpart + (int64_t)fy.nocc * fy.nocc + (int64_t)fy.nvir * fy.nvir;
+  }
+  p.n_rec = o;
+  int64_t noo = 0, nvv = 0;
+  std::vector<int32_t> inc_ptr(p.nfrag + 1, 0);
+  std::vector<int64_t> inc_base;
+  for (int f = 0; f < p.nfrag; ++f) {
+    off_oo[f] = noo;
+    off_vv[f] = nvv;
+    noo += (int64_t)p.frag[f].nocc * p.frag[f].nocc;
+    nvv += (int64_t)p.frag[f].nvir * p.frag[f].nvir;
+    auto& v = parts[f];
+    std::sort(v.begin(), v.end());
+    for (auto& e : v) inc_base.push_back(e.second);
+    inc_ptr[f + 1] = (int32_t)inc_base.size();
+  }
+  p.n_oo = noo;
+  p.n_vv = nvv;
+  hipError_t e = upload_vec(&p.d_cp_list, p.cp_list);
+  if (e == hipSuccess) e = upload_vec(&p.d_rec_off, rec_off);
+  if (e == hipSuccess) e = upload_vec(&p.d_off_oo, off_oo);
+  if (e == hipSuccess) e = upload_vec(&p.d_off_vv, off_vv);
+  if (e == hipSuccess) e = upload_vec(&p.d_inc_ptr, inc_ptr);
+  if (e == hipSuccess) e = upload_vec(&p.d_inc_base, inc_base);
+  return e;
+}
+
+// The coupled solve's workspace, then the pair records.
+int64_t dressing_ws_bytes(const fef_plan_s& p) {
+  return coupled_ws_bytes(p) + 8 * round_up(std::max<int64_t>(p.n_rec, 1), 32);
 }
 
 // Workspace: Y (B-pool sized), X (P_0 per C-pool element), then a region
@@ -661,10 +827,13 @@ int64_t coupled_ws_bytes(const fef_plan_s& p) {
   return 8 * (y + x + std::max<int64_t>(round_up(std::max<int64_t>(p.nB, 1), 32), slots));
 }
 
+// rec non-null: the solve kernels also write each pair's dressing record
+// (the workspace part after the coupled solve's, see dressing_ws_bytes)
 static hipError_t launch_coupled(const fef_plan_s& p, const double* B, const double* C,
                                  const double* eps, const double* G, double tol, int maxit,
                                  double* E2_pair, double* E2_total, int32_t* iters,
-                                 int32_t* flags, void* ws, hipStream_t st) {
+                                 int32_t* flags, void* ws, hipStream_t st,
+                                 double* rec = nullptr) {
   double* Y = static_cast<double*>(ws);
   double* X = Y + round_up(std::max<int64_t>(p.nB, 1), 32);
   double* H = X + round_up(std::max<int64_t>((int64_t)p.P0 * p.nC, 1), 32);
@@ -681,15 +850,27 @@ static hipError_t launch_coupled(const fef_plan_s& p, const double* B, const dou
       if (g.lds) {
         hipLaunchKernelGGL(coupled_cg_kernel<true>, dim3(g.nslots), dim3(kCgThreads), g.lds_bytes,
                            st, p.d_frag, p.d_pair, list, g.count, X, Y, p.P0, eps, slots, g.L,
-                           tol, maxit, E2_pair, iters, flags);
+                           tol, maxit, E2_pair, iters, flags, rec, p.d_rec_off);
       } else {
         hipLaunchKernelGGL(coupled_cg_kernel<false>, dim3(g.nslots), dim3(kCgThreads),
                            g.lds_bytes, st, p.d_frag, p.d_pair, list, g.count, X, Y, p.P0, eps,
-                           slots, g.L, tol, maxit, E2_pair, iters, flags);
+                           slots, g.L, tol, maxit, E2_pair, iters, flags, rec, p.d_rec_off);
       }
     }
   }
   hipLaunchKernelGGL(coupled_total_kernel, dim3(1), dim3(256), 0, st, E2_pair, p.npair, E2_total);
+  return hipGetLastError();
+}
+
+static hipError_t launch_dressing_reduce(const fef_plan_s& p, const double* rec, double* Hoo,
+                                         double* Hvv, hipStream_t st) {
+  if (p.nfrag == 0) return hipSuccess;
+  int64_t mx = 1;
+  for (const FragInfo& fi : p.frag)
+    mx = std::max<int64_t>(mx, (int64_t)fi.nocc * fi.nocc + (int64_t)fi.nvir * fi.nvir);
+  const unsigned gy = (unsigned)std::min<int64_t>((mx + 255) / 256, 64);
+  hipLaunchKernelGGL(dressing_reduce_kernel, dim3(p.nfrag, gy), dim3(256), 0, st, p.d_frag,
+                     p.d_inc_ptr, p.d_inc_base, p.d_off_oo, p.d_off_vv, rec, Hoo, Hvv);
   return hipGetLastError();
 }
 
@@ -732,6 +913,33 @@ fef_status fef_coupled_pair_energies(fef_plan p, const double* B, const double* 
                         static_cast<hipStream_t>(stream)) == hipSuccess
              ? FEF_OK
              : FEF_E_HIP;
+}
+
+fef_status fef_dimer_dressing(fef_plan p, const double* B, const double* C, const double* eps,
+                              const double* G, double tol, int32_t maxit, double* E2_pair,
+                              double* E2_total, double* Hoo, double* Hvv, int32_t* flags,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return FEF_E_ARG;
+  if (!E2_total || !flags) return FEF_E_ARG;
+  if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return FEF_E_ARG;
+  if (p->npair > 0 && (!B || !C || !eps || !G || !E2_pair || !ws)) return FEF_E_ARG;
+  if ((p->n_oo > 0 && !Hoo) || (p->n_vv > 0 && !Hvv)) return FEF_E_ARG;
+  if (p->npair > 0 && ws_bytes < (size_t)dressing_ws_bytes(*p)) return FEF_E_WORKSPACE;
+  if (p->max_nbf >= 2048) return FEF_E_UNSUPPORTED;
+  for (const auto& g : p->cp_groups)
+    if (g.lds_bytes > (size_t)kCgLdsMax) return FEF_E_UNSUPPORTED;
+  coupled_prepare();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* rec = ws ? reinterpret_cast<double*>(static_cast<char*>(ws) + coupled_ws_bytes(*p))
+                  : nullptr;
+  hipError_t e = launch_coupled(*p, B, C, eps, G, tol, maxit, E2_pair, E2_total, nullptr, flags,
+                                ws, st, p->npair > 0 ? rec : nullptr);
+  if (e == hipSuccess && p->npair > 0) e = launch_dressing_reduce(*p, rec, Hoo, Hvv, st);
+  else if (e == hipSuccess && p->nfrag > 0) {
+    // no pairs: every dressing is zero (a kernel, not a memset)
+    e = launch_dressing_reduce(*p, rec, Hoo, Hvv, st);
+  }
+  return e == hipSuccess ? FEF_OK : FEF_E_HIP;
 }
 
 }  // extern "C"

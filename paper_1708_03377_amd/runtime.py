@@ -145,6 +145,26 @@ class Context:
                                     self._cp_ws, self.stream())
         return self._cp_E[:self.npair], self._cp_tot, self._cp_it[:self.npair]
 
+    def dimer_dressing(self, tol: float = 1e-14, maxit: int = 0):
+        """Cross-fragment one-body dressings from the dimer doubles (maxit = 0:
+        the amplitudes -(ia|jb)/D of the pair energies; otherwise the
+        W^[0]-coupled ones); returns (E2_pair, E2_total, Hoo, Hvv) with the
+        per-fragment pools Hoo [nocc][nocc] and Hvv [nvir][nvir]."""
+        torch = self.torch
+        if getattr(self, "_dr_ws", None) is None:
+            self._dr_ws = torch.empty(max(self._q(F.Q_DRESSING_WS_BYTES), 1), dtype=torch.uint8,
+                                      device=self.device)
+            self._dr_E = torch.zeros(max(self.npair, 1), dtype=torch.float64, device=self.device)
+            self._dr_tot = torch.zeros(1, dtype=torch.float64, device=self.device)
+            self._dr_oo = torch.zeros(max(self._q(F.Q_HOO_ELEMS), 1), dtype=torch.float64,
+                                      device=self.device)
+            self._dr_vv = torch.zeros(max(self._q(F.Q_HVV_ELEMS), 1), dtype=torch.float64,
+                                      device=self.device)
+        F.fef_dimer_dressing(self.plan, self.B, self.C, self.eps, self.G, tol, maxit, self._dr_E,
+                             self._dr_tot, self._dr_oo, self._dr_vv, self.flags, self._dr_ws,
+                             self.stream())
+        return self._dr_E[:self.npair], self._dr_tot, self._dr_oo, self._dr_vv
+
     # ---- surrogate ---------------------------------------------------------
     def pair_energies_masked(self, prec: int, select):
         """Exact pair energies of the selected pairs; the others keep the

@@ -58,6 +58,8 @@ def test_null_arguments_rejected():
                             0, None) == F.FEF_E_ARG
     assert lib.fef_coupled_pair_energies(None, None, None, None, None, 1e-14, 10, None, None,
                                          None, None, None, 0, None) == F.FEF_E_ARG
+    assert lib.fef_dimer_dressing(None, None, None, None, None, 1e-14, 0, None, None, None, None,
+                                  None, None, 0, None) == F.FEF_E_ARG
 
 
 def test_coupled_flag_and_query_constants_match_header():
@@ -66,6 +68,8 @@ def test_coupled_flag_and_query_constants_match_header():
     txt = open(os.path.join(ROOT, "include", "fef.h")).read()
     assert re.search(rf"#define FEF_FLAG_NOCONV {F.FEF_FLAG_NOCONV}\b", txt)
     assert re.search(rf"FEF_Q_COUPLED_WS_BYTES = {F.Q_COUPLED_WS_BYTES}\b", txt)
+    for name in ("DRESSING_WS_BYTES", "HOO_ELEMS", "HVV_ELEMS"):
+        assert re.search(rf"FEF_Q_{name} = {getattr(F, 'Q_' + name)}\b", txt), name
 
 
 def test_bad_shapes_rejected_before_device():
