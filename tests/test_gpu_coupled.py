@@ -132,3 +132,23 @@ def test_coupled_thousand_waters_sampled_pairs(torch):
     _compare(E[idx], E_ref, "workload1 sample")
     # the total is the fixed-order sum of the pair energies
     assert float(tot.item()) == pytest.approx(float(np.sum(E)), rel=1e-12)
+
+
+def test_coupled_nucleobase_box_sampled_pairs(torch):
+    """Workload 2 (one nucleobase among 2000 waters, 2.4e5 pairs) in one call:
+    the 231 nucleobase-water pairs take the slot-resident path (their p and
+    W p exceed a workgroup's LDS).  The closest nucleobase-water pair and
+    three water pairs against the oracle."""
+    _say("coupled: workload 2 (nucleobase + 2000 waters), sampled pairs")
+    sysm = fefgen.make_system(2)
+    ctx = ctx_for(sysm)
+    E, tot, it = ctx.coupled_pair_energies()
+    torch.cuda.synchronize()
+    E = E.cpu().numpy()
+    assert int(ctx.flags.item()) == 0 and np.all(np.isfinite(E))
+    nb = np.nonzero((sysm.cls[sysm.pair_x] != 0) | (sysm.cls[sysm.pair_y] != 0))[0]
+    ww = np.nonzero((sysm.cls[sysm.pair_x] == 0) & (sysm.cls[sysm.pair_y] == 0))[0]
+    R = 1.0 / np.asarray(sysm.pair_s)
+    idx = [int(nb[np.argmin(R[nb])])] + [int(k) for k in ww[[0, len(ww) // 2, len(ww) - 1]]]
+    E_ref, _ = oc.coupled_pair_energies(sysm, pairs=idx)
+    _compare(E[idx], E_ref, "workload2 sample")
