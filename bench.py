@@ -589,6 +589,10 @@ def main():
         "accuracy_gate": {"bar_Eh": TOTAL_ERR_BAR, "against": "oracle" if ref_oracle is not None
                           else "gpu_f64", "oracle_total": ref_oracle},
         "scf_roofline": scf_stages,
+        # the SCF share of the timed captured pass: the pass less the half
+        # transform + pair energies unit timed alone on the same orbitals
+        "scf_in_pass_ms": round(h["gpu_ms_per_step"] - h["half_plus_pair"]["median_ms"], 4)
+        if h.get("half_plus_pair") else None,
         "coupled": coupled,
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],
         "speedup_vs_fp64": h["pairs_per_s"] / modes_out["f64"]["pairs_per_s"],
