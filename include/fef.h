@@ -17,7 +17,10 @@
  *     (fef_coulomb_field);
  *   - one polarisation-screened SCF update of every fragment
  *     F~ = F0 + h~ + J, (eps, C) = eigh(F~), Aufbau occupation
- *     (fef_scf_step; Sec. II.A, "Fragment Mean Field").
+ *     (fef_scf_step; Sec. II.A, "Fragment Mean Field");
+ *   - the dimer doubles coupled through W^[0] of Eq. partitioning0 and their
+ *     pair energies (fef_coupled_pair_energies), and the cross-fragment
+ *     one-body dressings of Eqs. MPij and MPab (fef_dimer_dressing).
  *
  * Integral model: (mu nu|lambda sigma)^{xy} = sum_PQ B^x_{P mu nu} T^{xy}_{PQ}
  * B^y_{Q lambda sigma} with T^{xy} = s_xy G_{c(x),c(y)}, s_xy = 1/R_xy
@@ -342,8 +345,10 @@ fef_status fef_pair_energies_noalloc(fef_plan plan, const void* ops, const doubl
  *   flags        : bit 1 for a non-finite energy, bit 2 when a pair stopped
  *                  at maxit without meeting tol.
  *   ws           : FEF_Q_COUPLED_WS_BYTES bytes (device).
- * Results are bitwise reproducible for a given plan.  A plan whose pairs
- * need more LDS than a workgroup has returns FEF_E_UNSUPPORTED. */
+ * One workgroup solves one pair; the search direction and its product live
+ * in LDS when they fit and in the workspace otherwise.  Results are bitwise
+ * reproducible for a given plan.  Plans with a fragment of 2048 or more
+ * basis functions return FEF_E_UNSUPPORTED. */
 fef_status fef_coupled_pair_energies(fef_plan plan, const double* B, const double* C,
                                      const double* eps, const double* G, double tol,
                                      int32_t maxit, double* E2_pair, double* E2_total,
