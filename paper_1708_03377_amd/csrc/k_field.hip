@@ -462,6 +462,9 @@ __global__ __launch_bounds__(256) void jbuild_packed_kernel(const FragInfo* __re
 // gather of one fragment is latency-bound and its J build streams the
 // fragment's coefficients, so workgroups in different phases overlap, and
 // phi stays in LDS.
+// Staged neighbour entries past a chunk of blockDim (the gather reads up to
+// 8 NG - 1 entries beyond a chunk's last, NG <= 8 groups)
+constexpr int kStageExtra = 64;
 __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
     const FragInfo* __restrict__ frag, const int32_t* __restrict__ nbr_ptr,
     const int32_t* __restrict__ nbr_idx, const double* __restrict__ nbr_s,
@@ -470,86 +473,86 @@ __global__ __launch_bounds__(512) void field_jbuild_packed_kernel(
     const int64_t* __restrict__ off_Bp, const double* __restrict__ Bp,
     const double* __restrict__ F0, const double* __restrict__ htilde, double* __restrict__ out,
     double* __restrict__ zero_out) {
-  extern __shared__ double part[];  // [NW][etot] per-wave partial e_c, then e; then phi^x
+  // LDS: the staged neighbour chunk (weights [NT + 64], pool offsets
+  // [NT + 64]), then [NW][etot] partial e_c (e after the reduction), then
+  // phi^x
+  extern __shared__ double smem[];
+  const int NT = blockDim.x, NW = NT >> 6;
+  double* st_s = smem;
+  int32_t* st_o = reinterpret_cast<int32_t*>(smem + NT + kStageExtra);
+  double* part = smem + NT + kStageExtra + (NT + kStageExtra) / 2;
+  __shared__ int32_t other_cls;
   // zero_out non-null: one thread clears it (a maximum that a later kernel
   // of the same step accumulates; set when no moments kernel runs)
   if (zero_out && blockIdx.x == 0 && threadIdx.x == 0) *zero_out = 0.0;
-  const int NW = blockDim.x >> 6;
   // fragments in reverse order: the moments kernel before it streamed the
   // slices forwards, so the last ones it read are the first ones read here
   const int x = gridDim.x - 1 - blockIdx.x;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int etot = naux_cls_off[nclass];
-  for (int t = threadIdx.x; t < NW * etot; t += blockDim.x) part[t] = 0.0;
-  __syncthreads();
-  double* mine = part + wave * etot;
+  for (int t = threadIdx.x; t < NW * etot; t += NT) part[t] = 0.0;
   const int beg = nbr_ptr[x], end = nbr_ptr[x + 1];
-  double e0 = 0.0, e1 = 0.0;
-  for (int c0 = beg + 64 * wave; c0 < end; c0 += 64 * NW) {
-    const int k = c0 + lane;
-    int y_cls = 0, y_naux = 0;
-    int64_t y_off = 0;
-    double y_s = 0.0;
-    if (k < end) {
-      const int y = nbr_idx[k];
-      y_s = nbr_s[k];
-      y_cls = frag[y].cls;
-      y_naux = frag[y].naux;
-      y_off = frag[y].off_aux;
-    }
-    const int cnt = min(64, end - c0);
-    // class-0 neighbours, four at a time: the weight of any other class is
-    // zeroed and its moments pointer parked at the pool start, so the loop
-    // has no branches and the four neighbours' loads are in flight together
-    // (four rather than eight keeps the kernel at 64 registers, eight waves
-    // per SIMD: 194 -> 183 us per step on the 4000-water box)
-    for (int j0 = 0; j0 < cnt; j0 += 4) {
-      double s8[4], v0[4], v1[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = min(j0 + u, cnt - 1);
-        const bool use = j0 + u < cnt && __builtin_amdgcn_readlane(y_cls, j) == 0;
-        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
-        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
-        const int64_t off = use ? (((int64_t)hi << 32) | (uint32_t)lo) : 0;
-        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
-                             0xffffffffLL;
-        const long long sh =
-            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
-        s8[u] = use ? __longlong_as_double((sh << 32) | sb) : 0.0;
-        const double* dy = dmom + off;
-        v0[u] = lane < P0 ? dy[lane] : 0.0;
-        v1[u] = lane + 64 < P0 ? dy[lane + 64] : 0.0;
+  // class-0 neighbours: NG groups of P0 threads, thread (g, q) sums
+  // s_xy d^y_q over the chunk's neighbours j = g, g + NG, ..., eight loads
+  // in flight; entries past the chunk carry weight 0 and offset 0, and a
+  // neighbour of another class is parked the same way (its sum is formed
+  // below), so the loop has no branches
+  const int NG = NT >= P0 ? min(NW, NT / P0) : 1;
+  for (int c0 = beg; c0 < end; c0 += NT) {
+    const int cnt = min(NT, end - c0);
+    if (threadIdx.x == 0) other_cls = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < NT + kStageExtra; t += NT) {
+      double s = 0.0;
+      int32_t o = 0;
+      if (t < cnt) {
+        const int y = nbr_idx[c0 + t];
+        const FragInfo fy = frag[y];
+        if (fy.cls == 0) {
+          s = nbr_s[c0 + t];
+          o = (int32_t)fy.off_aux;
+        } else {
+          other_cls = 1;
+        }
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        e0 = fma(s8[u], v0[u], e0);
-        e1 = fma(s8[u], v1[u], e1);
-      }
+      st_s[t] = s;
+      st_o[t] = o;
     }
-    // neighbours of other classes (rare): per-class sums in LDS
-    if (__any(k < end && y_cls != 0)) {
+    __syncthreads();
+    const int per = (cnt + NG - 1) / NG;
+    const int nb8 = (per + 7) / 8;
+    for (int u = threadIdx.x; u < NG * P0; u += NT) {
+      const int g = u / P0, q = u - g * P0;
+      double acc = 0.0;
+      for (int b = 0; b < nb8; ++b) {
+        const int j = g + 8 * NG * b;
+        double sv[8], dv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          sv[k] = st_s[j + k * NG];
+          dv[k] = dmom[st_o[j + k * NG] + q];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc = fma(sv[k], dv[k], acc);
+      }
+      part[g * etot + q] += acc;
+    }
+    // neighbours of other classes (rare): wave 0, one neighbour at a time,
+    // into the class sums of group 0
+    if (wave == 0 && other_cls) {
       for (int j = 0; j < cnt; ++j) {
-        const int cy = __builtin_amdgcn_readlane(y_cls, j);
-        if (cy == 0) continue;
-        const int lo = __builtin_amdgcn_readlane((int)y_off, j);
-        const int hi = __builtin_amdgcn_readlane((int)(y_off >> 32), j);
-        const int64_t off = ((int64_t)hi << 32) | (uint32_t)lo;
-        const long long sb = __builtin_amdgcn_readlane((int)__double_as_longlong(y_s), j) &
-                             0xffffffffLL;
-        const long long sh =
-            __builtin_amdgcn_readlane((int)(__double_as_longlong(y_s) >> 32), j);
-        const double s = __longlong_as_double((sh << 32) | sb);
-        const double* dy = dmom + off;
-        const int base = naux_cls_off[cy], pc = __builtin_amdgcn_readlane(y_naux, j);
-        for (int q = lane; q < pc; q += 64) mine[base + q] = fma(s, dy[q], mine[base + q]);
+        const int y = nbr_idx[c0 + j];
+        const FragInfo fy = frag[y];
+        if (fy.cls == 0) continue;
+        const double s = nbr_s[c0 + j];
+        const double* dy = dmom + fy.off_aux;
+        const int base = naux_cls_off[fy.cls];
+        for (int q = lane; q < fy.naux; q += 64) part[base + q] = fma(s, dy[q], part[base + q]);
       }
     }
   }
-  if (lane < P0) mine[lane] += e0;
-  if (lane + 64 < P0) mine[lane + 64] += e1;
   __syncthreads();
-  for (int q = threadIdx.x; q < etot; q += blockDim.x) {
+  for (int q = threadIdx.x; q < etot; q += NT) {
     double s = part[q];
     for (int w = 1; w < NW; ++w) s += part[w * etot + q];
     part[q] = s;
@@ -718,7 +721,10 @@ hipError_t launch_field_packed(const fef_plan_s& p, const double* Bp, const doub
   if (small_fragments(p)) {
     // all fragments small: field and J fused (water: 320 threads)
     const int jt = std::min(512, (ntmax + 63) / 64 * 64);
-    const size_t lds = ((size_t)(jt / 64) * etot + p.max_naux) * sizeof(double);
+    // the staged neighbour offsets are 32-bit
+    if (naux_total(p) > INT32_MAX) return hipErrorInvalidValue;
+    const size_t lds = ((size_t)(jt / 64) * etot + p.max_naux + (jt + kStageExtra) +
+                        (jt + kStageExtra) / 2) * sizeof(double);
     hipLaunchKernelGGL(field_jbuild_packed_kernel, dim3(p.nfrag), dim3(jt), lds, st, p.d_frag,
                        p.d_nbr_ptr, p.d_nbr_idx, p.d_nbr_s, G, p.d_off_G, p.P0, p.nclass,
                        p.d_naux_cls_off, ws_d, p.d_off_Bp, Bp, F0, htilde, out,
