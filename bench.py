@@ -173,27 +173,42 @@ def cpu_baseline(sysm, niter: int, budget_s: float):
                 break
     except OSError:
         pass
-    t0 = time.perf_counter()
-    C, e, _, _, _ = ofef.scf_step(sysm, sysm.C.copy(), sysm.eps.copy())
-    t_scf = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    remaining = max(budget_s - t_scf, 2.0)
-    n = min(sysm.npair, 1000)
-    t_pairs, done = 0.0, 0
-    while t_pairs < remaining and done < sysm.npair:
-        idx = rng.choice(sysm.npair, size=n, replace=False)
+
+    def sample(budget):
         t0 = time.perf_counter()
-        ofef.pair_energies(sysm, C, e, pairs=(sysm.pair_x[idx], sysm.pair_y[idx],
-                                              sysm.pair_s[idx]))
-        t_pairs += time.perf_counter() - t0
-        done += n
-    step_s = niter * t_scf + sysm.npair * (t_pairs / done)
-    return {"value": sysm.npair / step_s, "unit": "pairs/s", "cores": int(threads),
-            "kind": "oracle", "cpu_model": cpu_model, "blas": blas,
-            "affinity_cpus": len(os.sched_getaffinity(0)),
-            "sample": f"1 FP64 SCF step over all {sysm.nfrag} fragments ({t_scf:.2f} s) and "
-                      f"{done} random pairs ({t_pairs:.2f} s), scaled to {niter} SCF steps + "
-                      f"all {sysm.npair} pairs"}
+        C, e, _, _, _ = ofef.scf_step(sysm, sysm.C.copy(), sysm.eps.copy())
+        t_scf = time.perf_counter() - t0
+        rng = np.random.default_rng(0)
+        remaining = max(budget - t_scf, 2.0)
+        n = min(sysm.npair, 1000)
+        t_pairs, done = 0.0, 0
+        while t_pairs < remaining and done < sysm.npair:
+            idx = rng.choice(sysm.npair, size=n, replace=False)
+            t0 = time.perf_counter()
+            ofef.pair_energies(sysm, C, e, pairs=(sysm.pair_x[idx], sysm.pair_y[idx],
+                                                  sysm.pair_s[idx]))
+            t_pairs += time.perf_counter() - t0
+            done += n
+        step_s = niter * t_scf + sysm.npair * (t_pairs / done)
+        text = (f"1 FP64 SCF step over all {sysm.nfrag} fragments ({t_scf:.2f} s) and "
+                f"{done} random pairs ({t_pairs:.2f} s), scaled to {niter} SCF steps + "
+                f"all {sysm.npair} pairs")
+        return sysm.npair / step_s, text
+
+    value, text = sample(budget_s)
+    out = {"value": value, "unit": "pairs/s", "cores": int(threads),
+           "kind": "oracle", "cpu_model": cpu_model, "blas": blas,
+           "affinity_cpus": len(os.sched_getaffinity(0)), "sample": text}
+    # the same sample on one BLAS thread (half the budget)
+    try:
+        import threadpoolctl
+        with threadpoolctl.threadpool_limits(1):
+            v1, t1 = sample(0.5 * budget_s)
+        out["value_1thread"] = v1
+        out["sample_1thread"] = t1
+    except ImportError:
+        pass
+    return out
 
 
 def coupled_flops(sysm, iters) -> float:

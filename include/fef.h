@@ -70,6 +70,7 @@ typedef int32_t fef_status;
 #define FEF_E_WORKSPACE -4    /* workspace too small                   */
 #define FEF_E_HIP -5          /* HIP runtime error                     */
 #define FEF_E_UNSUPPORTED -6  /* valid request the library cannot do   */
+#define FEF_E_IO -7           /* a file could not be written           */
 
 #define FEF_FLAG_GAP 1
 #define FEF_FLAG_NONFINITE 2
@@ -289,6 +290,25 @@ fef_status fef_graph_destroy(fef_graph graph);
 fef_status fef_autotune(fef_plan plan, const void* ops, const double* eps, fef_prec prec,
                         void* ws, size_t ws_bytes, int32_t reps, void* stream,
                         int32_t* best_xb, int32_t* best_yc, double* best_us);
+
+/* The autotuner with a persisted cache, for processes that run the same
+ * work again: `cache_path` names a JSON file mapping
+ * "<GPU architecture>/<mode>/<work signature>" to the chosen tiling and its
+ * time, the signature a hash of the fragment shapes and classes and the
+ * oriented pair list (what the pair kernel's schedule depends on).  On a
+ * hit the cached tiling is applied (fef_plan_set_tiles), nothing is timed,
+ * best_us is the cached time and *from_cache = 1.  Otherwise it runs
+ * fef_autotune, then rewrites the file with the entry added or replaced
+ * (through a temporary file renamed over it) and *from_cache = 0.  A missing
+ * or unreadable file is an empty cache; lines that are not entries are
+ * skipped.  Returns FEF_E_IO when the file cannot be written (the tuned
+ * tiling is applied all the same).  Concurrent writers of one file: the
+ * last rename wins.  Allocates like fef_autotune on a miss: call outside
+ * capture. */
+fef_status fef_autotune_cached(fef_plan plan, const void* ops, const double* eps, fef_prec prec,
+                               void* ws, size_t ws_bytes, int32_t reps, void* stream,
+                               const char* cache_path, int32_t* best_xb, int32_t* best_yc,
+                               double* best_us, int32_t* from_cache);
 
 /* Pair energies of the selected pairs only (Eqs. ED2, dimDoubles, as
  * fef_pair_energies): select [npair] device int32, nonzero = evaluate.

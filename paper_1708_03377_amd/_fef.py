@@ -22,6 +22,7 @@ FEF_E_PREC = -3
 FEF_E_WORKSPACE = -4
 FEF_E_HIP = -5
 FEF_E_UNSUPPORTED = -6
+FEF_E_IO = -7
 FEF_FLAG_GAP = 1
 FEF_FLAG_NONFINITE = 2
 FEF_FLAG_NOCONV = 4
@@ -47,7 +48,7 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
                 "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_plan_stage_timing",
                 "fef_plan_stage_ms", "fef_coupled_pair_energies", "fef_dimer_dressing",
-                "fef_status_string")
+                "fef_autotune_cached", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -100,6 +101,9 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
     lib.fef_graph_destroy.argtypes = [vp]
     lib.fef_autotune.argtypes = [vp, vp, vp, i32, vp, sz, i32, vp, ctypes.POINTER(i32),
                                  ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    lib.fef_autotune_cached.argtypes = [vp, vp, vp, i32, vp, sz, i32, vp, ctypes.c_char_p,
+                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     f32, f64 = ctypes.c_float, ctypes.c_double
     lib.fef_pair_energies_masked.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
     lib.fef_coupling_modes.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -307,6 +311,15 @@ def fef_autotune(plan, ops, eps, prec, ws, reps=3, stream=None):
         plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(ws), _nbytes(ws), reps, _stream(stream),
         ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us)))
     return xb.value, yc.value, us.value
+
+
+def fef_autotune_cached(plan, ops, eps, prec, ws, cache_path, reps=3, stream=None):
+    xb, yc, us, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check("fef_autotune_cached", load_library().fef_autotune_cached(
+        plan.handle, _ptr(ops), _ptr(eps), prec, _ptr(ws), _nbytes(ws), reps, _stream(stream),
+        path, ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us), ctypes.byref(hit)))
+    return xb.value, yc.value, us.value, bool(hit.value)
 
 
 def fef_pair_energies_masked(plan, ops, eps, prec, select, E2_pair, E2_total, flags, ws,

@@ -128,6 +128,7 @@ const char* fef_status_string(fef_status s) {
     case FEF_E_WORKSPACE: return "workspace too small";
     case FEF_E_HIP: return "HIP runtime error";
     case FEF_E_UNSUPPORTED: return "unsupported request";
+    case FEF_E_IO: return "file could not be written";
     default: return "unknown status";
   }
 }

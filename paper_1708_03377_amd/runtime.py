@@ -124,6 +124,13 @@ class Context:
         return F.fef_autotune(self.plan, self.ops_for(prec), self.eps, prec, self.ws, reps,
                               self.stream())
 
+    def autotune_cached(self, prec: int, cache_path: str, reps: int = 3):
+        """autotune through a persisted cache file: (xb, yc, us, from_cache)
+        (runs the half transform first)."""
+        self.half_transform(prec)
+        return F.fef_autotune_cached(self.plan, self.ops_for(prec), self.eps, prec, self.ws,
+                                     cache_path, reps, self.stream())
+
     def energies(self, prec: int):
         """Half transform + pair energies on the current orbitals."""
         self.half_transform(prec)

@@ -277,6 +277,48 @@ def test_autotune_keeps_results(torch):
         assert np.max(np.abs(E2 - ref)) <= (TOL_PAIR_F64 if prec == "f64" else 1e-6)
 
 
+def test_autotune_cache_file(torch, tmp_path):
+    """fef_autotune_cached: a miss tunes and writes the entry, a hit applies
+    the cached tiling without timing and gives bitwise the same energies;
+    another system adds a second entry; lines that are not entries are
+    skipped; an unwritable path reports FEF_E_IO with the tiling in place."""
+    import json
+
+    import paper_1708_03377_amd as lib
+    from paper_1708_03377_amd import _fef as F
+    _say("autotune cache: workload 0 and the ragged system, fp16x2")
+    path = str(tmp_path / "tiles.json")
+    p = PREC["fp16x2"]
+    sysm = fefgen.make_system(0)
+    ctx = ctx_for(sysm)
+    xb, yc, us, hit = ctx.autotune_cached(p, path, reps=2)
+    assert not hit and us > 0
+    assert lib.fef_plan_get_tiles(ctx.plan, p) == (xb, yc)
+    E_tuned = ctx.pair_energies(p)[0].cpu().numpy().copy()
+    cache = json.load(open(path))
+    assert len(cache) == 1
+    key = next(iter(cache))
+    assert key.split("/")[1] == "fp16x2" and cache[key]["xb"] == xb and cache[key]["yc"] == yc
+    # a new context on the same work: served from the cache, same tiles and energies
+    ctx2 = ctx_for(sysm)
+    xb2, yc2, us2, hit2 = ctx2.autotune_cached(p, path, reps=2)
+    assert hit2 and (xb2, yc2) == (xb, yc) and us2 == pytest.approx(us, rel=1e-3, abs=0.1)
+    assert lib.fef_plan_get_tiles(ctx2.plan, p) == (xb, yc)
+    assert np.array_equal(ctx2.pair_energies(p)[0].cpu().numpy(), E_tuned)
+    # other work: a miss, and the file keeps both entries (plus a stray line)
+    with open(path, "a") as f:
+        f.write("not an entry\n")
+    ctx3 = ctx_for(ragged_system())
+    _, _, _, hit3 = ctx3.autotune_cached(p, path, reps=2)
+    assert not hit3
+    assert len(json.load(open(path))) == 2
+    # an unwritable cache path
+    bad = str(tmp_path / "no_such_dir" / "tiles.json")
+    with pytest.raises(F.FefError) as ei:
+        ctx3.autotune_cached(p, bad, reps=1)
+    assert ei.value.status == F.FEF_E_IO
+
+
 @pytest.mark.parametrize("which,niter", [("config0", 3), ("ragged", 2), ("two_class", 2)])
 def test_packed_scf_matches_oracle(torch, which, niter):
     """SCF steps on the packed (upper-triangle) coefficients against the

@@ -41,6 +41,7 @@ def test_status_strings():
     assert F.fef_status_string(0) == "ok"
     assert "workspace" in F.fef_status_string(F.FEF_E_WORKSPACE)
     assert F.fef_status_string(-99) == "unknown status"
+    assert "file" in F.fef_status_string(F.FEF_E_IO)
 
 
 def test_null_arguments_rejected():
@@ -60,6 +61,10 @@ def test_null_arguments_rejected():
                                          None, None, None, 0, None) == F.FEF_E_ARG
     assert lib.fef_dimer_dressing(None, None, None, None, None, 1e-14, 0, None, None, None, None,
                                   None, None, 0, None) == F.FEF_E_ARG
+    xb, yc, us, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
+    assert lib.fef_autotune_cached(None, None, None, 3, None, 0, 3, None, b"/tmp/x.json",
+                                   ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us),
+                                   ctypes.byref(hit)) == F.FEF_E_ARG
 
 
 def test_coupled_flag_and_query_constants_match_header():
@@ -67,6 +72,7 @@ def test_coupled_flag_and_query_constants_match_header():
     F, lib = _lib()
     txt = open(os.path.join(ROOT, "include", "fef.h")).read()
     assert re.search(rf"#define FEF_FLAG_NOCONV {F.FEF_FLAG_NOCONV}\b", txt)
+    assert re.search(rf"#define FEF_E_IO {F.FEF_E_IO}\b", txt)
     assert re.search(rf"FEF_Q_COUPLED_WS_BYTES = {F.Q_COUPLED_WS_BYTES}\b", txt)
     for name in ("DRESSING_WS_BYTES", "HOO_ELEMS", "HVV_ELEMS"):
         assert re.search(rf"FEF_Q_{name} = {getattr(F, 'Q_' + name)}\b", txt), name
