@@ -532,14 +532,22 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
     double dold[M];  // this lane's row of the previous density, loaded up front
 #pragma unroll
     for (int j = 0; j < M; ++j) dold[j] = Dold[oc + t * n + (j < n ? j : 0)];
+    // row t of the density, all columns at once: per occupied slot one
+    // entry of this row and the slot's column (read by every lane of the
+    // half alike), the products added in slot order as before
+    double dacc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) dacc[j] = 0.0;
+    for (int k = 0; k < nocc; ++k) {
+      const int sl = occ[h][k];
+      const double ov = s1[t * LD + sl];
+#pragma unroll
+      for (int j = 0; j < M; ++j) dacc[j] = fma(ov, s1[j * LD + sl], dacc[j]);
+    }
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       if (j < n) {
-        double acc = 0.0;
-        for (int k = 0; k < nocc; ++k) {
-          const int sl = occ[h][k];
-          acc = fma(s1[t * LD + sl], s1[j * LD + sl], acc);
-        }
+        const double acc = dacc[j];
         Dnew[oc + t * n + j] = acc;
         // the weighted packed copy, exactly as the density kernel forms it
         if (Dw && t <= j) {
