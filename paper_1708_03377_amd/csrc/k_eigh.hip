@@ -380,6 +380,15 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
   // loads are unconditional (positions outside the matrix read its first
   // element and are replaced by zero), so that each lane's loads are in
   // flight together.
+  // The Fock row and column of this lane are loaded together with the
+  // orbitals, so that the two loads' latencies overlap.
+  double frow[M], fcol[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const bool in = t < n && k < n;
+    frow[k] = F[oc + (in ? t * n + k : 0)];
+    fcol[k] = F[oc + (in ? k * n + t : 0)];
+  }
   {
     constexpr int kPer = (M * M + 31) / 32;
     double cv[kPer];
@@ -398,13 +407,6 @@ __global__ __launch_bounds__(64, 2) void eigh_wave_kernel(
   }
   __syncthreads();
   if (t < M) {
-    double frow[M], fcol[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      const bool in = t < n && k < n;
-      frow[k] = F[oc + (in ? t * n + k : 0)];
-      fcol[k] = F[oc + (in ? k * n + t : 0)];
-    }
 #pragma unroll
     for (int k = 0; k < M; ++k) frow[k] = (t < n && k < n) ? 0.5 * (frow[k] + fcol[k]) : 0.0;
 #pragma unroll
