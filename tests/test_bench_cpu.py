@@ -73,3 +73,14 @@ def test_coupled_flops_counts_blocks_and_products():
     build = 2 * 72 * (95 * 95 + 361 ** 2 + 95 ** 2 + 95 ** 2 + 25 ** 2)
     apply = 2 * (361 ** 2 * 25 + 95 ** 2 * 95 * 2 + 25 ** 2 * 361)
     assert bench.coupled_flops(sysm, [8]) == build + 9 * apply
+
+
+def test_cpu_baseline_reports_all_cores_and_one_thread():
+    """The oracle sample on the default BLAS threads and again on one; both
+    scaled to a full step of the workload (8 waters here, a short budget)."""
+    s = fefgen.make_system(0)
+    cb = bench.cpu_baseline(s, 10, 1.0)
+    assert cb["kind"] == "oracle" and cb["unit"] == "pairs/s" and cb["cores"] >= 1
+    assert cb["value"] > 0 and np.isfinite(cb["value"])
+    assert "all 28 pairs" in cb["sample"]
+    assert cb.get("value_1thread", 0) > 0 and "all 28 pairs" in cb["sample_1thread"]
