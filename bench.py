@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--surrogate-threshold", type=float, default=1e-8,
                     help="ensemble spread (Eh) above which a pair falls back to the exact kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-monomer", action="store_true",
+                    help="skip the monomer-energy block")
     ap.add_argument("--no-coupled", action="store_true",
                     help="skip the coupled dimer-doubles block")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -275,6 +277,57 @@ def coupled_cpu_baseline(sysm, C, eps, npairs: int = 8):
     dt = time.perf_counter() - t0
     return {"value": len(idx) / dt, "unit": "pairs/s", "kind": "oracle",
             "sample": f"{len(idx)} random pairs, CG to 1e-14 ({dt:.2f} s)"}
+
+
+def monomer_work(sysm):
+    """Algorithmic FP64 work of fef_monomer_energies: per fragment the GEMM
+    V = W^T B_ov over P_0 (2 ov^2 P_0 flops) and the exchange-weighted sum
+    over every (ia, jb) (6 flops each); HBM bytes: B_ov and W read once
+    (2 P_0 ov doubles), the fragment's orbital energies and one result."""
+    ov = (sysm.nocc * (sysm.nbf - sysm.nocc)).astype(np.float64)
+    P0 = float(sysm.naux_class[0])
+    flops = float(np.sum(2 * ov ** 2 * P0 + 6 * ov ** 2))
+    nbytes = float(np.sum(8 * (2 * P0 * ov + sysm.nbf + 1)))
+    return flops, nbytes
+
+
+def bench_monomer(ctx, sysm, torch, st, F, reps: int = 5):
+    """The monomer energies E_M2 (FP64 MFMA) on the current orbitals: the
+    half transform writes the dense B_ov and W once, then the monomer call
+    alone is timed with events on its stream."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    E, tot = ctx.monomer_energies()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        a, b = ev(), ev()
+        a.record(st)
+        F.fef_monomer_energies(ctx.plan, ctx._mo_bov, ctx._mo_w, ctx.eps, ctx._mo_E,
+                               ctx._mo_tot, ctx.flags, st)
+        b.record(st)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    t = float(np.mean(ms))
+    flops, nbytes = monomer_work(sysm)
+    return {"ms": round(t, 4), "reps": reps, "fragments_per_s": sysm.nfrag / (t / 1e3),
+            "E_M2_total": float(ctx._mo_tot.item()), "flags": int(ctx.flags.item()),
+            "roofline": {"kernel": "monomer_energy_kernel (FP64 MFMA)", "bound": "mfma",
+                         "achieved": flops / (t / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": flops / (t / 1e3) / 78.6e12, "algorithmic_flops": flops,
+                         "algorithmic_bytes": nbytes,
+                         "hbm_GBps": nbytes / (t / 1e3) / 1e9,
+                         "note": "whole call (per-fragment kernel and the fixed-order total)"}}
+
+
+def monomer_cpu_baseline(sysm, C, eps, nfrag: int = 200):
+    """The monomer oracle on a sample of fragments of the same box."""
+    from oracle import monomer as om
+    idx = np.random.default_rng(2).choice(sysm.nfrag, size=min(nfrag, sysm.nfrag), replace=False)
+    t0 = time.perf_counter()
+    om.monomer_energies(sysm, C, eps, frags=idx)
+    dt = time.perf_counter() - t0
+    return {"value": len(idx) / dt, "unit": "fragments/s", "kind": "oracle",
+            "sample": f"{len(idx)} random fragments ({dt:.2f} s)"}
 
 
 # pair modes timed per workload when --modes is not given
@@ -521,6 +574,20 @@ def main():
         print("[bench] coupled dimer doubles", file=sys.stderr, flush=True)
         coupled = bench_coupled(ctx, sysm, torch, st)
         coupled_C, coupled_eps = ctx.C.cpu().numpy(), ctx.eps.cpu().numpy()
+    monomer = None
+    if not args.no_monomer and int(np.max(sysm.cls)) == 0:
+        print("[bench] monomer energies", file=sys.stderr, flush=True)
+        from paper_1708_03377_amd import _fef
+        # on the workload's final orbitals (the SCF stage timing above ran
+        # further steps)
+        ctx.reset_orbitals()
+        ctx.scf(niter)
+        monomer = bench_monomer(ctx, sysm, torch, st, _fef)
+        gm = os.path.join(ROOT, "tests", "golden", f"{spec.name}_monomer_oracle.npz")
+        if os.path.exists(gm):
+            monomer["oracle_total"] = float(np.load(gm, allow_pickle=False)["total"])
+            monomer["err_vs_oracle"] = monomer["E_M2_total"] - monomer["oracle_total"]
+        monomer_C, monomer_eps = ctx.C.cpu().numpy(), ctx.eps.cpu().numpy()
     ref = results["f64"]
     ref_oracle = oracle_total(spec.name)
     ref_total = ref_oracle if ref_oracle is not None else ref["E_total"]
@@ -609,6 +676,7 @@ def main():
         "scf_in_pass_ms": round(h["gpu_ms_per_step"] - h["half_plus_pair"]["median_ms"], 4)
         if h.get("half_plus_pair") else None,
         "coupled": coupled,
+        "monomer": monomer,
         "fp64_pairs_per_s": modes_out["f64"]["pairs_per_s"],
         "speedup_vs_fp64": h["pairs_per_s"] / modes_out["f64"]["pairs_per_s"],
         "modes": modes_out,
@@ -618,6 +686,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(sysm, niter, args.cpu_seconds)
         if coupled is not None:
             coupled["cpu_baseline"] = coupled_cpu_baseline(sysm, coupled_C, coupled_eps)
+        if monomer is not None:
+            monomer["cpu_baseline"] = monomer_cpu_baseline(sysm, monomer_C, monomer_eps)
     print(json.dumps(line), flush=True)
 
 

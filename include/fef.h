@@ -397,6 +397,28 @@ fef_status fef_dimer_dressing(fef_plan plan, const double* B, const double* C, c
                               double* E2_total, double* Hoo, double* Hvv, int32_t* flags,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Monomer part of the second-order energy (Sec. II.B, Eq. EFEF2): for every
+ * fragment the contraction of its two-body de-excitation operator with its
+ * first-order doubles (Eq. EM2), the doubles solving Eq. monDoubles with the
+ * two-body part of H0 dropped (as for the pair energies), summed over spin:
+ *   E_M2^x = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)]
+ *                       / (eps_i + eps_j - eps_a - eps_b),
+ * i, j occupied and a, b virtual orbitals of fragment x.  The integrals
+ * inside a fragment are the factored tensor with the solvent class's own
+ * coupling block at unit scale: (ia|jb) = sum_PQ B_ov[P][ia] G_{0,0}[P][Q]
+ * B_ov[Q][jb] = sum_Q W[Q][ia] B_ov[Q][jb].
+ *   Bov, W   : the dense FP64 outputs of fef_half_transform (device).
+ *   eps      : orbital-energy pool (device).
+ *   E_M2     : [nfrag] out, per fragment (device).
+ *   E_M2_total : [1] out, FP64 sum over fragments in a fixed order (device).
+ *   flags    : bit 1 is OR-ed in when a fragment energy is not finite.
+ * Every fragment must be of class 0 (no other class has a coupling block
+ * with itself): otherwise FEF_E_SHAPE.  nocc * nvir above 128 returns
+ * FEF_E_UNSUPPORTED.  No workspace; bitwise reproducible. */
+fef_status fef_monomer_energies(fef_plan plan, const double* Bov, const double* W,
+                                const double* eps, double* E_M2, double* E_M2_total,
+                                int32_t* flags, void* stream);
+
 /* ------------------------------------------------------------------------
  * Distant-pair surrogate.  A project addition: the paper has no learned
  * component.  It predicts E2_xy of Eq. ED2 for distant pairs from

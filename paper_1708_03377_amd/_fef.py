@@ -48,7 +48,7 @@ ENTRY_POINTS = ("fef_plan_create", "fef_plan_destroy", "fef_plan_query",
                 "fef_mlp_train_ws_bytes", "fef_surrogate_select", "fef_pack_coefficients",
                 "fef_scf_step_packed", "fef_pair_energies_noalloc", "fef_plan_stage_timing",
                 "fef_plan_stage_ms", "fef_coupled_pair_energies", "fef_dimer_dressing",
-                "fef_autotune_cached", "fef_status_string")
+                "fef_autotune_cached", "fef_monomer_energies", "fef_status_string")
 
 
 class FefError(RuntimeError):
@@ -123,6 +123,7 @@ def load_library(path: Optional[str] = None) -> ctypes.CDLL:
                                               sz, vp]
     lib.fef_dimer_dressing.argtypes = [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp, vp, sz,
                                        vp]
+    lib.fef_monomer_energies.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     lib.fef_plan_stage_timing.argtypes = [vp, i32]
     lib.fef_plan_stage_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fef_status_string.argtypes = [i32]
@@ -253,6 +254,12 @@ def fef_coupled_pair_energies(plan, B, C, eps, G, tol, maxit, E2_pair, E2_total,
     _check("fef_coupled_pair_energies", load_library().fef_coupled_pair_energies(
         plan.handle, _ptr(B), _ptr(C), _ptr(eps), _ptr(G), float(tol), int(maxit), _ptr(E2_pair),
         _ptr(E2_total), _ptr(iters), _ptr(flags), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def fef_monomer_energies(plan, Bov, W, eps, E_M2, E_M2_total, flags, stream=None):
+    _check("fef_monomer_energies", load_library().fef_monomer_energies(
+        plan.handle, _ptr(Bov), _ptr(W), _ptr(eps), _ptr(E_M2), _ptr(E_M2_total), _ptr(flags),
+        _stream(stream)))
 
 
 def fef_dimer_dressing(plan, B, C, eps, G, tol, maxit, E2_pair, E2_total, Hoo, Hvv, flags, ws,

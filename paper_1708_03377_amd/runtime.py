@@ -172,6 +172,25 @@ class Context:
                              self.stream())
         return self._dr_E[:self.npair], self._dr_tot, self._dr_oo, self._dr_vv
 
+    def monomer_energies(self, prec: int = 0):
+        """E_M2 of every fragment on the current orbitals (Eq. EM2): the half
+        transform in mode `prec` with its dense FP64 B_ov and W outputs, then
+        the monomer kernel; returns (per-fragment energies, their sum).  The
+        output buffers are allocated on first use."""
+        torch = self.torch
+        if getattr(self, "_mo_E", None) is None:
+            self._mo_bov = torch.empty(max(self.sizes["bov"], 1), dtype=torch.float64,
+                                       device=self.device)
+            self._mo_w = torch.empty(max(self.sizes["w"], 1), dtype=torch.float64,
+                                     device=self.device)
+            self._mo_E = torch.zeros(max(self.system.nfrag, 1), dtype=torch.float64,
+                                     device=self.device)
+            self._mo_tot = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.half_transform(prec, self._mo_bov, self._mo_w)
+        F.fef_monomer_energies(self.plan, self._mo_bov, self._mo_w, self.eps, self._mo_E,
+                               self._mo_tot, self.flags, self.stream())
+        return self._mo_E[:self.system.nfrag], self._mo_tot
+
     # ---- surrogate ---------------------------------------------------------
     def pair_energies_masked(self, prec: int, select):
         """Exact pair energies of the selected pairs; the others keep the

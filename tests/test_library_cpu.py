@@ -61,6 +61,8 @@ def test_null_arguments_rejected():
                                          None, None, None, 0, None) == F.FEF_E_ARG
     assert lib.fef_dimer_dressing(None, None, None, None, None, 1e-14, 0, None, None, None, None,
                                   None, None, 0, None) == F.FEF_E_ARG
+    assert lib.fef_monomer_energies(None, None, None, None, None, None, None,
+                                    None) == F.FEF_E_ARG
     xb, yc, us, hit = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32()
     assert lib.fef_autotune_cached(None, None, None, 3, None, 0, 3, None, b"/tmp/x.json",
                                    ctypes.byref(xb), ctypes.byref(yc), ctypes.byref(us),
