@@ -280,13 +280,15 @@ def coupled_cpu_baseline(sysm, C, eps, npairs: int = 8):
 
 
 def monomer_work(sysm):
-    """Algorithmic FP64 work of fef_monomer_energies: per fragment the GEMM
-    V = W^T B_ov over P_0 (2 ov^2 P_0 flops) and the exchange-weighted sum
-    over every (ia, jb) (6 flops each); HBM bytes: B_ov and W read once
-    (2 P_0 ov doubles), the fragment's orbital energies and one result."""
+    """Algorithmic FP64 work of fef_monomer_energies: per fragment the
+    symmetric block V = W^T B_ov = B_ov^T G_{0,0} B_ov over P_0, of which
+    ov (ov + 1) / 2 elements are needed (2 P_0 flops each), and the
+    exchange-weighted sum over every (ia, jb) (6 flops each); HBM bytes: B_ov
+    and W read once (2 P_0 ov doubles), the fragment's orbital energies and
+    one result."""
     ov = (sysm.nocc * (sysm.nbf - sysm.nocc)).astype(np.float64)
     P0 = float(sysm.naux_class[0])
-    flops = float(np.sum(2 * ov ** 2 * P0 + 6 * ov ** 2))
+    flops = float(np.sum(P0 * ov * (ov + 1) + 6 * ov ** 2))
     nbytes = float(np.sum(8 * (2 * P0 * ov + sysm.nbf + 1)))
     return flops, nbytes
 

@@ -413,8 +413,9 @@ fef_status fef_dimer_dressing(fef_plan plan, const double* B, const double* C, c
  *   E_M2_total : [1] out, FP64 sum over fragments in a fixed order (device).
  *   flags    : bit 1 is OR-ed in when a fragment energy is not finite.
  * Every fragment must be of class 0 (no other class has a coupling block
- * with itself): otherwise FEF_E_SHAPE.  nocc * nvir above 128 returns
- * FEF_E_UNSUPPORTED.  No workspace; bitwise reproducible. */
+ * with itself): otherwise FEF_E_SHAPE.  nocc * nvir above 128 or P_0
+ * above 80 returns FEF_E_UNSUPPORTED.  No workspace; bitwise
+ * reproducible. */
 fef_status fef_monomer_energies(fef_plan plan, const double* Bov, const double* W,
                                 const double* eps, double* E_M2, double* E_M2_total,
                                 int32_t* flags, void* stream);
