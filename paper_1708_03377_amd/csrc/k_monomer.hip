@@ -46,6 +46,26 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline int mono_ld(int ov) { return ov | 1; }
 
+// Row strip of each wave.  Strip s forms NT - s tiles (those on and right of
+// the diagonal); the waves of a workgroup sit on the four SIMDs in turn
+// (wave w on SIMD w % 4), so the strips are dealt longest first to the
+// SIMD with the least work so far (-1: no strip).
+template <int NT>
+struct StripMap {
+  int strip[kMonoWaves];
+  constexpr StripMap() : strip() {
+    int load[4] = {0, 0, 0, 0};
+    for (int w = 0; w < kMonoWaves; ++w) strip[w] = -1;
+    for (int s = 0; s < NT; ++s) {
+      int best = -1;
+      for (int w = 0; w < kMonoWaves; ++w)
+        if (strip[w] < 0 && (best < 0 || load[w % 4] < load[best % 4])) best = w;
+      strip[best] = s;
+      load[best % 4] += NT - s;
+    }
+  }
+};
+
 // NT: column tiles of the launch (ceil(max ov / 16)); a fragment with fewer
 // reads zeros for the rest, so the product loops have no branches
 template <int NT>
@@ -67,8 +87,12 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_energy_kernel(
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int li = lane & 15, lk = lane >> 4;
   const int nt = (ov + 15) >> 4;
-  const bool gemm = wave < nt && P > 0;
-  const int m = wave * 16 + li;
+  constexpr StripMap<NT> kMap;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int sp = kMap.strip[wv];  // this wave's row strip
+  const bool has_strip = sp >= 0 && sp < nt;
+  const bool gemm = has_strip && P > 0;
+  const int m = sp * 16 + li;
   const int mc = min(m, ov - 1);
   // this wave's W strip, A[m][k] = W[k][m], every k step loaded at once:
   // rows past P read row P - 1 and columns past ov column ov - 1, and are
@@ -114,7 +138,6 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_energy_kernel(
 
   // V is symmetric (G_{0,0} is), so each wave forms only the tiles of its
   // row strip on and right of the diagonal and mirrors them
-  const int wv = __builtin_amdgcn_readfirstlane(wave);
   d4v acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = d4v{0.0, 0.0, 0.0, 0.0};
@@ -131,22 +154,22 @@ __global__ __launch_bounds__(kMonoThreads) void monomer_energy_kernel(
       for (int t = 0; t < NT; ++t) b[t] = V[kr + min(t * 16 + li, ov - 1)];
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        if (t >= wv) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[s2], b[t], acc[t], 0, 0, 0);
+        if (t >= sp) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[s2], b[t], acc[t], 0, 0, 0);
     }
   }
   __syncthreads();  // every wave is done with the staged B_ov
-  if (wave < nt) {
+  if (has_strip) {
     // FP64 MFMA result: row lk + 4 r, column li of each 16 x 16 tile
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      if (t < wv) continue;
+      if (t < sp) continue;
       const int n = t * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wave * 16 + lk + 4 * r;
+        const int row = sp * 16 + lk + 4 * r;
         if (row < ov && n < ov) {
           V[row * ld + n] = acc[t][r];
-          if (t > wv) V[n * ld + row] = acc[t][r];
+          if (t > sp) V[n * ld + row] = acc[t][r];
         }
       }
     }
