@@ -191,6 +191,16 @@ class Context:
                                self._mo_tot, self.flags, self.stream())
         return self._mo_E[:self.system.nfrag], self._mo_tot
 
+    def correlation_energy(self, prec: int = 0):
+        """Second-order correlation energy E_M2 + E_D2 (Eq. EFEF2) on the
+        current orbitals: the monomer energies and the pair energies in mode
+        `prec` (one half transform serves both); returns
+        (E_M2, E_D2, E_M2 + E_D2) as floats."""
+        _, em2 = self.monomer_energies(prec)
+        _, ed2 = self.pair_energies(prec)
+        em2, ed2 = float(em2.cpu()[0]), float(ed2.cpu()[0])
+        return em2, ed2, em2 + ed2
+
     # ---- surrogate ---------------------------------------------------------
     def pair_energies_masked(self, prec: int, select):
         """Exact pair energies of the selected pairs; the others keep the

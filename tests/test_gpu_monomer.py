@@ -99,6 +99,20 @@ def test_after_scf_against_the_oracles_scf(torch):
     _compare(E.cpu().numpy(), ref, "after SCF", rel=1e-10, abs_=1e-14)
 
 
+def test_correlation_energy_of_workload0(torch):
+    """E_corr = E_M2 + E_D2 (Eq. EFEF2) on the generated orbitals against the
+    two oracle sums."""
+    s = fefgen.make_system(0)
+    _say("case: 8 waters, E_M2 + E_D2")
+    ctx = _ctx(s)
+    em2, ed2, tot = ctx.correlation_energy()
+    ref_m, ref_m_tot = om.monomer_energies(s)
+    _, ref_d = ofef.pair_energies(s)
+    assert em2 == pytest.approx(ref_m_tot, rel=1e-13)
+    assert ed2 == pytest.approx(ref_d, rel=1e-12)
+    assert tot == pytest.approx(ref_m_tot + ref_d, rel=1e-13)
+
+
 def test_rejections(torch):
     import paper_1708_03377_amd as lib
     from paper_1708_03377_amd import _fef as F
