@@ -325,10 +325,16 @@ def monomer_cpu_baseline(sysm, C, eps, nfrag: int = 200):
     """The monomer oracle on a sample of fragments of the same box."""
     from oracle import monomer as om
     idx = np.random.default_rng(2).choice(sysm.nfrag, size=min(nfrag, sysm.nfrag), replace=False)
+    threads = 1
+    try:
+        import threadpoolctl
+        threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except ImportError:
+        pass
     t0 = time.perf_counter()
     om.monomer_energies(sysm, C, eps, frags=idx)
     dt = time.perf_counter() - t0
-    return {"value": len(idx) / dt, "unit": "fragments/s", "kind": "oracle",
+    return {"value": len(idx) / dt, "unit": "fragments/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(idx)} random fragments ({dt:.2f} s)"}
 
 
