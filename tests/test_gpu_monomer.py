@@ -84,6 +84,17 @@ def test_ragged_shapes_and_repeatability(torch):
     assert np.array_equal(E2.cpu().numpy(), E1) and float(t2.cpu()[0]) == t1
 
 
+def test_largest_factor_rank(torch):
+    """P_0 = 80, the largest factor rank (every register k step in use),
+    with the largest ov and a water-sized fragment."""
+    s = fefgen.make_random_system(35, [(24, 8), (24, 5), (11, 2)], naux=80)
+    _say("case: P = 80, ov = 128, 95, 18")
+    ctx = _ctx(s)
+    E, _ = ctx.monomer_energies()
+    ref, _ = om.monomer_energies(s)
+    _compare(E.cpu().numpy(), ref, "P = 80")
+
+
 def test_after_scf_against_the_oracles_scf(torch):
     s = fefgen.make_random_system(32, [(24, 5), (13, 4), (24, 5), (9, 2), (24, 5)], naux=16,
                                   spacing=3.0)
