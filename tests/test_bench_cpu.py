@@ -84,3 +84,13 @@ def test_cpu_baseline_reports_all_cores_and_one_thread():
     assert cb["value"] > 0 and np.isfinite(cb["value"])
     assert "all 28 pairs" in cb["sample"]
     assert cb.get("value_1thread", 0) > 0 and "all 28 pairs" in cb["sample_1thread"]
+
+
+def test_monomer_work_counts_the_symmetric_block():
+    """Per water (ov = 95, P_0 = 72): the needed half of the symmetric
+    block, 72 * 95 * 96 flops, plus 6 flops per (ia, jb); B_ov and W read
+    once (2 * 72 * 95 doubles), 24 orbital energies and one result."""
+    s = fefgen.make_system(0)
+    flops, nbytes = bench.monomer_work(s)
+    assert flops == s.nfrag * (72 * 95 * 96 + 6 * 95 * 95)
+    assert nbytes == s.nfrag * 8 * (2 * 72 * 95 + 24 + 1)
